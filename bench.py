@@ -1,0 +1,165 @@
+"""Throughput of the CPIC leapfrog hot path on one MI355X.
+
+Workload (the method's plain SU(3) configuration): 512 x 64 x 64 lattice, SU(3),
+a_T = 4 a_L, dt = a_L/2, two MV nuclei (mu = 0.5, sigma = 8 a_L, m = 0.2,
+Lambda = 10/a_T), initial state built on the GPU.  One step = one leapfrog update of
+every link and E field with the CPIC charge hop on every second step; observables
+(T^{mu nu} slices, Gauss residual, energy) are reduced every 16 steps inside the
+timed region.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: site-updates/s of the FP64 single-event form (value), the
+roofline of the dominant kernel (the fused leapfrog step) from HIP events on the
+library's stream, the FP32 form, and the oracle timed on the host CPU.
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_site_update(nc, fp, dt_over_aL):
+    """Minimum HBM traffic of one site-update: read + write U and E once, plus read +
+    write of both charge populations on hop steps (a fraction dt/a_L of the steps)."""
+    b = 8 if fp == 64 else 4
+    r = 4 if nc == 2 else 18
+    ng = nc * nc - 1
+    u = 2 * 3 * r * b
+    e = 2 * 3 * ng * b
+    rho = 2 * 2 * ng * b * dt_over_aL
+    return u + e + rho
+
+
+def run_gpu(w, fp, steps, warmup, obs_every=16):
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=fp,
+                      reunit_every=8 if fp == 32 else 0)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    obs = lat.obs_buffer()
+    torch.cuda.synchronize()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    # whole hot path: steps + observables every obs_every steps
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(obs_every, steps - done)
+        lat.step(n)
+        done += n
+        lat.observe(obs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # dominant kernel alone, HIP events on the library's stream
+    st = lat.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    lat.step(steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    o = pkg.Lattice.unpack_obs(obs, w.nz)
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "kernel_ms": kern_ms,
+            "site_updates_per_s": w.sites * steps / wall, "gauss_rel": o["gauss_rel"],
+            "energy": o["energy"], "unitarity": o["unitarity"]}
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: a 64-layer slab of the
+    beam axis at the full transverse size, stepped until ~budget_s of CPU time."""
+    import synth
+    from oracle import lattice, init_mv
+    nz = 64
+    ws = synth.Workload("slab", nc=w.nc, nz=nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, mu=w.mu,
+                        sigma=w.sigma, m_ir=w.m_ir, uv_cut=w.uv_cut, seed=w.seed)
+    p = lattice.Params(ws.nc, ws.a_T, ws.a_L, ws.dt)
+    mv = init_mv.MVParams(ws.m_ir, ws.uv_cut, ws.sigma, ws.zA, ws.zB)
+    rA, rB = synth.mv_charges(ws.seed, ws.nc, ws.nt, ws.mu, ws.a_T)
+    st, _ = init_mv.initial_state(rA, rB, nz, p, mv)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        st = lattice.leapfrog_step(st)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 8:
+            break
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return {"value": ws.sites * n / wall, "unit": "site-updates/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": f"{n} leapfrog steps of a {nz}x{ws.nt}x{ws.nt} slab (SU({ws.nc}), FP64 NumPy)",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=256)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import synth
+    w = synth.PLAIN_SU3
+    r64 = run_gpu(w, 64, args.steps, args.warmup)
+    print(f"[bench] fp64 {w.name}: {r64['site_updates_per_s']:.3e} site-updates/s, "
+          f"kernel {r64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    forms = {}
+    if not args.no_fp32:
+        r32 = run_gpu(w, 32, args.steps, args.warmup)
+        b32 = algorithmic_bytes_per_site_update(3, 32, w.dt / w.a_L)
+        forms["fp32_plain"] = {"site_updates_per_s": r32["site_updates_per_s"],
+                               "kernel_ms": r32["kernel_ms"],
+                               "hbm_frac": b32 * w.sites / (r32["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "gauss_rel": r32["gauss_rel"], "unitarity": r32["unitarity"]}
+        print(f"[bench] fp32 {w.name}: {r32['site_updates_per_s']:.3e} site-updates/s", file=sys.stderr,
+              flush=True)
+    bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
+    achieved = bpsu * w.sites / (r64["kernel_ms"] * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w)
+        print(f"[bench] cpu oracle: {cpu['value']:.3e} site-updates/s", file=sys.stderr, flush=True)
+    line = {
+        "metric": "site-updates/s (SU(3) FP64 leapfrog + CPIC, single event)",
+        "value": r64["site_updates_per_s"],
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (MV charges, seeded)",
+        "config": {"workload": w.name, "nc": 3, "lattice": [w.nz, w.nt, w.nt], "a_T": w.a_T,
+                   "dt": w.dt, "scheme": "leapfrog", "obs_every": 16},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_leapfrog<Su3<double>,double>", "kernel_ms": r64["kernel_ms"],
+                     "bytes_per_site_update": bpsu},
+        "checks": {"gauss_rel": r64["gauss_rel"], "unitarity": r64["unitarity"]},
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

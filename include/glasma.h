@@ -1,0 +1,179 @@
+/*
+ * glasma.h -- C-ABI of the MI355X (gfx950) library for the 3+1D Glasma
+ * colored-particle-in-cell (CPIC) evolution of Ipp & Mueller, "Progress on 3+1D
+ * Glasma simulations" (arXiv:2009.02044).
+ *
+ * The library evolves SU(2) or SU(3) gauge links U_i(x) and Lie-algebra electric
+ * fields E_i(x) on an nz x nt x nt lattice (z = beam axis, periodic in all three
+ * directions), driven by the colour charges of two nuclei that move at the speed of
+ * light along -z (nucleus A) and +z (nucleus B).
+ *
+ * Conventions (lattice units; the coupling g is absorbed into the fields):
+ *   spacings a_x = a_y = a_T, a_z = a_L; time step dt with dt/a_L rational in (0, 1].
+ *   site index s = (z * nt + y) * nt + x; V = nz * nt * nt.
+ *   Generators t^a = sigma^a/2 (SU(2)) or lambda^a/2 (SU(3)); n_g = nc^2 - 1.
+ *   Algebra fields are stored by components X^a = 2 Tr(t^a X).
+ *   E_i and j_i are the continuum-normalised fields: the paper's E and j in
+ *   eqs. lattice_1/2 (Sec. 3) equal a_i E_i and a_i j_i.  One step is
+ *     E_i(t+dt/2) = E_i(t-dt/2) + dt [ -(1/a_i) sum_{j!=i} a_j^-2 P(U_{i,j} + U_{i,-j}) + j_i ]
+ *     U_i(t+dt)   = exp(i a_i dt E_i(t+dt/2)) U_i(t)
+ *   with P(M) the hermitian traceless part of (M - M^dag)/(2i) (the paper's [M]_ah is
+ *   i P(M)), and the Gauss law (eq. gauss) reads
+ *     sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)] / a_i = rho_A(x) + rho_B(x).
+ *
+ * Host array layout (all host arrays are double, structure of arrays):
+ *   links  U[i][c][s], i = 0:x 1:y 2:z; SU(2): c = 0..3, U = u0 + i (u1 s1 + u2 s2 + u3 s3);
+ *          SU(3): c = 2 (3 r + k) + {0 Re, 1 Im} for matrix entry (r, k)
+ *   E      E[i][a][s];  charges rho[a][s] at their physical lattice positions.
+ * Device buffers use the same ordering in the context's precision (fp = 64: double,
+ * fp = 32: float); the charge buffers are stored co-moving with their nucleus, so
+ * read them through glasma_get_state.
+ *
+ * Memory: the caller allocates every device buffer (sizes from glasma_layout) and
+ * keeps it alive until glasma_destroy; the library never allocates or frees device
+ * memory itself.  The context holds only host metadata.
+ * Streams: all device work is enqueued on the stream given to glasma_create; calls
+ * return without waiting unless stated otherwise.
+ * Errors: every call returns GLASMA_OK (0) or a negative code; no exception crosses
+ * the ABI.  glasma_last_error(ctx) (or NULL for failures without a context) gives
+ * a message.  A context is not thread safe.
+ */
+#ifndef GLASMA_H
+#define GLASMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GLASMA_OK 0
+#define GLASMA_E_ARG (-1)        /* invalid argument or size */
+#define GLASMA_E_HIP (-2)        /* HIP runtime error (message kept) */
+#define GLASMA_E_NONFINITE (-3)  /* NaN / Inf found in the fields */
+#define GLASMA_E_CONSTRAINT (-4) /* Gauss residual above the requested bound */
+#define GLASMA_E_NOCONV (-5)     /* semi-implicit iteration reached max_iter */
+#define GLASMA_E_STATE (-6)      /* call out of order (e.g. step before init) */
+
+typedef struct glasma_ctx glasma_ctx;
+
+typedef struct {
+  int32_t nc;           /* 2 or 3: gauge group SU(nc) */
+  int32_t nz, nt;       /* lattice nz (beam axis) x nt x nt; nz >= 2, nt >= 2 */
+  double a_T, a_L, dt;  /* spacings and time step, dt/a_L rational in (0, 1] */
+  int32_t fp;           /* 64 or 32: storage and arithmetic precision of U, E, rho */
+  int32_t scheme;       /* 0: leapfrog (eqs. lattice_1/2); 1: semi-implicit (Sec. 3) */
+  int32_t reunit_every; /* > 0: reunitarise links (FP64 arithmetic) every k steps */
+  int32_t max_iter;     /* semi-implicit: fixed-point iteration cap */
+  double tol;           /* semi-implicit: convergence bound on max |dE| / max |E| */
+} glasma_params;
+
+/* Device buffers (caller-owned; sizes in bytes from glasma_layout, same order). */
+typedef struct {
+  void* U;      /* links at the current time, 3 * r_U * V reals (r_U = 4 or 18) */
+  void* U_alt;  /* second link buffer of the same size (the step writes into it) */
+  void* E;      /* electric field, 3 * n_g * V reals */
+  void* rhoA;   /* charges of nucleus A, n_g * V reals (co-moving storage) */
+  void* rhoB;   /* charges of nucleus B, n_g * V reals (co-moving storage) */
+  void* work;   /* scratch: initial conditions, reductions, iterations */
+} glasma_buffers;
+
+/* Initial-condition parameters (Sec. 2 Poisson solution; Sec. 3 eq. single_sheet). */
+typedef struct {
+  double m_ir;    /* IR regulator m of the transverse Poisson equation (> 0) */
+  double uv_cut;  /* UV cutoff Lambda on |k~| (<= 0: none) */
+  double sigma;   /* width of the Gaussian longitudinal profile (units of length) */
+  double zA, zB;  /* centres of nucleus A (moving -z) and B (moving +z) at t0 */
+} glasma_mv;
+
+/* Number of doubles glasma_observe writes: 4 * nz slices + GLASMA_OBS_NSCALARS. */
+#define GLASMA_OBS_NSCALARS 8
+/* Scalar slots after the 4 * nz slices (eps, p_L, p_T, S_L per layer, each the
+ * transverse mean at that layer). */
+#define GLASMA_OBS_ENERGY 0      /* H = a_T^2 a_L sum_x eps */
+#define GLASMA_OBS_GAUSS_L2 1    /* ||G||_2 over all sites and colours */
+#define GLASMA_OBS_RHO_L2 2      /* ||rho||_2 */
+#define GLASMA_OBS_GAUSS_MAX 3   /* max_x,a |G^a(x)| */
+#define GLASMA_OBS_UNITARITY 4   /* max over links of |U^dag U - 1| and |det U - 1| */
+#define GLASMA_OBS_NONFINITE 5   /* number of sites with a NaN / Inf */
+#define GLASMA_OBS_GAUSS_REL 6   /* ||G||_2 / ||rho||_2 (||G||_2 if rho = 0) */
+
+/* Library version string. */
+const char* glasma_version(void);
+
+/* Message of the last failure on ctx (NULL: the last failure without a context). */
+const char* glasma_last_error(const glasma_ctx* ctx);
+
+/* Byte sizes of the six glasma_buffers entries for params p (bytes[6]). */
+int glasma_layout(const glasma_params* p, size_t* bytes);
+
+/* Create a context over caller-owned device buffers b on HIP stream `stream`
+ * (a hipStream_t; NULL = default stream).  The buffers are not read here. */
+int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream, glasma_ctx** out);
+
+/* Destroy the context (host memory only; the caller frees its buffers). */
+int glasma_destroy(glasma_ctx* ctx);
+
+/* Upload a state from host double arrays in the layout above (charges at physical
+ * positions).  The state is U(t), E(t - dt/2), rho(t - dt/2) with t = t0 + step0 dt;
+ * step0 fixes the phase of the charge hop schedule.  Synchronous. */
+int glasma_init_state(glasma_ctx* ctx, const double* U, const double* E, const double* rhoA,
+                      const double* rhoB, int64_t step0);
+
+/* Build the MV initial state on the GPU (Sec. 2 and 3) from the transverse colour
+ * charges rhoT_A, rhoT_B (host double, [n_g][nt][nt] each; the random draw of the
+ * MV ensemble is an input).  Sets step = 0.  Asynchronous after the upload. */
+int glasma_init_mv(glasma_ctx* ctx, const glasma_mv* mv, const double* rhoT_A, const double* rhoT_B);
+
+/* Advance n >= 0 steps (leapfrog or semi-implicit per params, CPIC hops on the steps
+ * the schedule S(s) = floor((s + 1/2) dt/a_L + 1/2) advances, reunitarisation every
+ * reunit_every steps when set).  Asynchronous for the leapfrog. */
+int glasma_step(glasma_ctx* ctx, int32_t n);
+
+/* Current j (device, 3 * n_g * V reals of the context's precision, layout of E) that
+ * the next step deposits: j_z = (a_L/dt)(rho_A' - rho_B) on hop steps (rho_A' is
+ * the transported A charge), zero otherwise (Sec. 3, eq. continuity).  Does not
+ * change the state.  Asynchronous. */
+int glasma_deposit_current(glasma_ctx* ctx, void* j_out);
+
+/* Observables at the current integer time into device memory d_out (double,
+ * 4 * nz + GLASMA_OBS_NSCALARS): eps, p_L, p_T, S_L slices (Sec. 4, <T^{mu nu}> and
+ * eq. pT_eL) computed in double precision, then the scalars listed above.  Does not
+ * change the state.  Asynchronous. */
+int glasma_observe(glasma_ctx* ctx, double* d_out);
+
+/* Synchronous variant to host memory: tmunu_z [4][nz] (may be NULL) and scalars
+ * (each may be NULL). */
+int glasma_observables(glasma_ctx* ctx, double* tmunu_z, double* gauss_rel, double* gauss_max,
+                       double* energy, double* unitarity_max);
+
+/* Download the state to host double arrays (layout above; charges at physical
+ * positions; any pointer may be NULL) and the step counter.  Synchronous. */
+int glasma_get_state(glasma_ctx* ctx, double* U, double* E, double* rhoA, double* rhoB,
+                     int64_t* step);
+
+/* Project every link back onto SU(nc) in double arithmetic (SU(2): q/|q|; SU(3):
+ * Gram-Schmidt of rows 1, 2, row 3 = conj(r1 x r2)).  Asynchronous. */
+int glasma_reunitarize(glasma_ctx* ctx);
+
+/* Current step counter (host value). */
+int glasma_get_step(const glasma_ctx* ctx, int64_t* step);
+
+/* Host-side evaluation of the library's group kernels, for CPU tests of the
+ * device algebra (the same inline functions the GPU kernels use).  op:
+ *   0: out = exp(i s X) as a link      in = [s, X^a]                (n_g + 1 in)
+ *   1: out = -i Log(W) components      in = W link reals             (r_U in)
+ *   2: out = P(M) components           in = M link reals             (r_U in)
+ *   3: out = U^dag X U components      in = [U link reals, X^a]      (r_U + n_g in)
+ *   4: out = reunitarised link         in = link reals
+ *   5: out = [unitarity violation]     in = link reals
+ *   6: out = A B (link)                in = [A, B] link reals
+ * fp = 64 or 32 selects the arithmetic.  n items are processed; in/out are packed
+ * item after item.  Returns GLASMA_E_ARG for an unknown op. */
+int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const double* in, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLASMA_H */

@@ -193,3 +193,35 @@ def gauge_transform(st, Omega):
     rA = su.mul(Omega, st.rhoA, su.dag(Omega))
     rB = su.mul(Omega, st.rhoB, su.dag(Omega))
     return State(U, E, rA, rB, st.step, st.params)
+
+
+def force_at_site(U, a, site):
+    """F_i at one site (z, y, x) by direct indexing: the same formula as force(),
+    evaluated for a single site so that full-size lattices can be sampled."""
+    nz, ny, nx = U.shape[1:4]
+
+    def at(i, pos):
+        z, y, x = pos
+        return U[i, z % nz, y % ny, x % nx]
+
+    def sh(pos, i, d):
+        z, y, x = pos
+        if i == 0:
+            return (z, y, x + d)
+        if i == 1:
+            return (z, y + d, x)
+        return (z + d, y, x)
+
+    out = []
+    for i in range(3):
+        acc = 0
+        for j in range(3):
+            if j == i:
+                continue
+            xpi = sh(site, i, 1)
+            up = at(i, site) @ at(j, xpi) @ su.dag(at(i, sh(site, j, 1))) @ su.dag(at(j, site))
+            xmj = sh(site, j, -1)
+            dn = at(i, site) @ su.dag(at(j, sh(xpi, j, -1))) @ su.dag(at(i, xmj)) @ at(j, xmj)
+            acc = acc + su.proj(up + dn) / a[j] ** 2
+        out.append(-acc / a[i])
+    return np.stack(out)

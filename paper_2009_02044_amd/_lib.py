@@ -1,0 +1,88 @@
+"""ctypes binding of libglasma.so (argument marshalling only).
+
+The library is loaded from this package directory; a missing or unloadable library
+raises at import of the binding so that no caller can silently fall back to another
+implementation.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglasma.so")
+
+GLASMA_OK = 0
+ERRORS = {-1: "GLASMA_E_ARG", -2: "GLASMA_E_HIP", -3: "GLASMA_E_NONFINITE",
+          -4: "GLASMA_E_CONSTRAINT", -5: "GLASMA_E_NOCONV", -6: "GLASMA_E_STATE"}
+OBS_NSCALARS = 8
+OBS = {"energy": 0, "gauss_l2": 1, "rho_l2": 2, "gauss_max": 3, "unitarity": 4,
+       "nonfinite": 5, "gauss_rel": 6}
+
+
+class Params(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
+                ("a_T", C.c_double), ("a_L", C.c_double), ("dt", C.c_double),
+                ("fp", C.c_int32), ("scheme", C.c_int32), ("reunit_every", C.c_int32),
+                ("max_iter", C.c_int32), ("tol", C.c_double)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("U", C.c_void_p), ("U_alt", C.c_void_p), ("E", C.c_void_p),
+                ("rhoA", C.c_void_p), ("rhoB", C.c_void_p), ("work", C.c_void_p)]
+
+
+class MV(C.Structure):
+    _fields_ = [("m_ir", C.c_double), ("uv_cut", C.c_double), ("sigma", C.c_double),
+                ("zA", C.c_double), ("zB", C.c_double)]
+
+
+class GlasmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_02044_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, D, I32, I64, V = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_void_p
+    sig = {
+        "glasma_version": ([], C.c_char_p),
+        "glasma_last_error": ([P], C.c_char_p),
+        "glasma_layout": ([C.POINTER(Params), C.POINTER(C.c_size_t)], C.c_int),
+        "glasma_create": ([C.POINTER(Params), C.POINTER(Buffers), V, C.POINTER(P)], C.c_int),
+        "glasma_destroy": ([P], C.c_int),
+        "glasma_init_state": ([P, D, D, D, D, I64], C.c_int),
+        "glasma_init_mv": ([P, C.POINTER(MV), D, D], C.c_int),
+        "glasma_step": ([P, I32], C.c_int),
+        "glasma_deposit_current": ([P, V], C.c_int),
+        "glasma_observe": ([P, V], C.c_int),
+        "glasma_observables": ([P, D, D, D, D, D], C.c_int),
+        "glasma_get_state": ([P, D, D, D, D, C.POINTER(I64)], C.c_int),
+        "glasma_reunitarize": ([P], C.c_int),
+        "glasma_get_step": ([P, C.POINTER(I64)], C.c_int),
+        "glasma_host_group_op": ([I32, I32, I32, I64, D, D], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def check(rc, ctx=None):
+    if rc != GLASMA_OK:
+        msg = lib.glasma_last_error(ctx)
+        raise GlasmaError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def dptr(a):
+    """double* of a C-contiguous float64 numpy array (or None)."""
+    if a is None:
+        return None
+    assert a.dtype.name == "float64" and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))

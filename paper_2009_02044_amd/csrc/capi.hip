@@ -1,0 +1,395 @@
+// C-ABI of the library (declared in include/glasma.h): context, argument checks,
+// the integer charge-hop schedule, host <-> device state transfer and dispatch to
+// the templated kernels for (SU(2) | SU(3)) x (double | float).
+#include <string>
+#include <vector>
+#include <cstring>
+#include <cstdio>
+#include <cmath>
+#include "internal.h"
+#include "../../include/glasma.h"
+
+using namespace gl;
+
+struct glasma_ctx {
+  glasma_params p;
+  glasma_buffers b;
+  hipStream_t stream;
+  Geom g;
+  int ng, r;
+  int64_t step;
+  int cur;            // 0: links live in b.U, 1: in b.U_alt
+  int offA, offB;     // co-moving charge storage offsets (mod nz)
+  int64_t hop_p, hop_q;  // dt / a_L = hop_p / hop_q
+  bool ready;
+  std::string err;
+};
+
+static std::string g_err;
+
+static int fail(glasma_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m; else g_err = m;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(ctx, GLASMA_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static bool rational(double r, int64_t* p, int64_t* q) {
+  for (int64_t d = 1; d <= 4096; ++d) {
+    double n = std::round(r * d);
+    if (std::fabs(n / d - r) < 1e-12 && n >= 1) { *p = (int64_t)n; *q = d; return true; }
+  }
+  return false;
+}
+
+// S(s) = floor((s + 1/2) dt/a_L + 1/2) = floor(((2s + 1) p + q) / (2 q)) for s >= -1.
+static int64_t hop_count(const glasma_ctx* c, int64_t s) {
+  int64_t num = (2 * s + 1) * c->hop_p + c->hop_q;
+  int64_t den = 2 * c->hop_q;
+  return num >= 0 ? num / den : -((-num + den - 1) / den);
+}
+static bool is_hop(const glasma_ctx* c, int64_t s) { return hop_count(c, s) > hop_count(c, s - 1); }
+
+static size_t elem(const glasma_params* p) { return p->fp == 64 ? 8 : 4; }
+
+static int check_params(const glasma_params* p, int64_t* hp, int64_t* hq) {
+  if (!p) return fail(nullptr, GLASMA_E_ARG, "params is NULL");
+  if (p->nc != 2 && p->nc != 3) return fail(nullptr, GLASMA_E_ARG, "nc must be 2 or 3");
+  if (p->nz < 2 || p->nt < 2) return fail(nullptr, GLASMA_E_ARG, "nz and nt must be >= 2");
+  if ((int64_t)p->nz * p->nt * p->nt > (int64_t)1 << 31) return fail(nullptr, GLASMA_E_ARG, "lattice too large");
+  if (p->fp != 64 && p->fp != 32) return fail(nullptr, GLASMA_E_ARG, "fp must be 64 or 32");
+  if (!(p->a_T > 0) || !(p->a_L > 0) || !(p->dt > 0)) return fail(nullptr, GLASMA_E_ARG, "spacings and dt must be > 0");
+  if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, GLASMA_E_ARG, "scheme must be 0 or 1");
+  if (p->reunit_every < 0) return fail(nullptr, GLASMA_E_ARG, "reunit_every must be >= 0");
+  int64_t a, b;
+  if (!rational(p->dt / p->a_L, &a, &b) || a > b)
+    return fail(nullptr, GLASMA_E_ARG, "dt/a_L must be a rational number in (0, 1] with denominator <= 4096");
+  if (hp) *hp = a;
+  if (hq) *hq = b;
+  return GLASMA_OK;
+}
+
+static Geom geom_of(const glasma_params* p) {
+  Geom g;
+  g.nt = p->nt;
+  g.nz = p->nz;
+  g.layer = (int64_t)p->nt * p->nt;
+  g.V = g.layer * p->nz;
+  return g;
+}
+
+static size_t work_doubles(const glasma_params* p) {
+  Geom g = geom_of(p);
+  int ng = p->nc * p->nc - 1;
+  size_t ic = ic_work_doubles(g, ng);
+  size_t obs = observe_partial_doubles(g) + 4 * (size_t)g.nz + GLASMA_OBS_NSCALARS;
+  size_t w = ic > obs ? ic : obs;
+  return w;
+}
+
+template <class F> static int dispatch(glasma_ctx* c, F&& f) {
+  if (c->p.nc == 2 && c->p.fp == 64) return f.template operator()<Su2<double>, double>();
+  if (c->p.nc == 3 && c->p.fp == 64) return f.template operator()<Su3<double>, double>();
+  if (c->p.nc == 2 && c->p.fp == 32) return f.template operator()<Su2<float>, float>();
+  return f.template operator()<Su3<float>, float>();
+}
+
+static StepConst step_const(const glasma_ctx* c) {
+  StepConst k;
+  k.a[0] = c->p.a_T; k.a[1] = c->p.a_T; k.a[2] = c->p.a_L;
+  k.dt = c->p.dt;
+  k.hop = is_hop(c, c->step) ? 1 : 0;
+  k.offA = c->offA;
+  k.offB = c->offB;
+  return k;
+}
+
+template <typename T> static T* cur_U(glasma_ctx* c) { return (T*)(c->cur ? c->b.U_alt : c->b.U); }
+template <typename T> static T* next_U(glasma_ctx* c) { return (T*)(c->cur ? c->b.U : c->b.U_alt); }
+
+// The functions below have C linkage through their declarations in glasma.h.
+
+const char* glasma_version(void) { return "glasma-mi355x 0.1 (gfx950)"; }
+
+const char* glasma_last_error(const glasma_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int glasma_layout(const glasma_params* p, size_t* bytes) {
+  int rc = check_params(p, nullptr, nullptr);
+  if (rc) return rc;
+  if (!bytes) return fail(nullptr, GLASMA_E_ARG, "bytes is NULL");
+  Geom g = geom_of(p);
+  const size_t e = elem(p);
+  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  bytes[0] = 3 * (size_t)r * g.V * e;
+  bytes[1] = bytes[0];
+  bytes[2] = 3 * (size_t)ng * g.V * e;
+  bytes[3] = (size_t)ng * g.V * e;
+  bytes[4] = bytes[3];
+  bytes[5] = work_doubles(p) * sizeof(double);
+  return GLASMA_OK;
+}
+
+int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream, glasma_ctx** out) {
+  int64_t hp, hq;
+  int rc = check_params(p, &hp, &hq);
+  if (rc) return rc;
+  if (!b || !out) return fail(nullptr, GLASMA_E_ARG, "buffers or out is NULL");
+  if (!b->U || !b->U_alt || !b->E || !b->rhoA || !b->rhoB || !b->work)
+    return fail(nullptr, GLASMA_E_ARG, "a device buffer is NULL");
+  if (p->scheme == 1) return fail(nullptr, GLASMA_E_ARG, "scheme 1 is not available in this build");
+  glasma_ctx* c = new glasma_ctx();
+  c->p = *p;
+  c->b = *b;
+  c->stream = (hipStream_t)stream;
+  c->g = geom_of(p);
+  c->ng = p->nc * p->nc - 1;
+  c->r = p->nc == 2 ? 4 : 18;
+  c->step = 0;
+  c->cur = 0;
+  c->offA = c->offB = 0;
+  c->hop_p = hp;
+  c->hop_q = hq;
+  c->ready = false;
+  *out = c;
+  return GLASMA_OK;
+}
+
+int glasma_destroy(glasma_ctx* ctx) {
+  delete ctx;
+  return GLASMA_OK;
+}
+
+int glasma_get_step(const glasma_ctx* ctx, int64_t* step) {
+  if (!ctx || !step) return fail(nullptr, GLASMA_E_ARG, "NULL argument");
+  *step = ctx->step;
+  return GLASMA_OK;
+}
+
+template <typename T>
+static int upload(glasma_ctx* c, void* dst, const double* src, size_t n) {
+  std::vector<T> tmp(n);
+  for (size_t k = 0; k < n; ++k) tmp[k] = (T)src[k];
+  HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GLASMA_OK;
+}
+
+int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const double* rhoA, const double* rhoB,
+                      int64_t step0) {
+  if (!c || !U || !E || !rhoA || !rhoB) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (step0 < 0) return fail(c, GLASMA_E_ARG, "step0 must be >= 0");
+  const size_t V = c->g.V;
+  int rc = dispatch(c, [&]<typename G, typename T>() -> int {
+    int r;
+    if ((r = upload<T>(c, c->b.U, U, 3 * (size_t)c->r * V))) return r;
+    if ((r = upload<T>(c, c->b.E, E, 3 * (size_t)c->ng * V))) return r;
+    if ((r = upload<T>(c, c->b.rhoA, rhoA, (size_t)c->ng * V))) return r;
+    if ((r = upload<T>(c, c->b.rhoB, rhoB, (size_t)c->ng * V))) return r;
+    return GLASMA_OK;
+  });
+  if (rc) return rc;
+  c->cur = 0;
+  c->offA = c->offB = 0;
+  c->step = step0;
+  c->ready = true;
+  return GLASMA_OK;
+}
+
+int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, const double* rhoT_B) {
+  if (!c || !mv || !rhoT_A || !rhoT_B) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (!(mv->m_ir > 0) || !(mv->sigma > 0)) return fail(c, GLASMA_E_ARG, "m_ir and sigma must be > 0");
+  const size_t m = (size_t)c->ng * c->g.layer;
+  double* work = (double*)c->b.work;
+  HIPCHK(c, hipMemcpyAsync(work, rhoT_A, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(work + m, rhoT_B, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  McvConst k{mv->m_ir, mv->uv_cut, mv->sigma, mv->zA, mv->zB};
+  c->step = 0;
+  c->cur = 0;
+  c->offA = c->offB = 0;
+  StepConst sc = step_const(c);
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_init_mv<G, T>(work, work, (T*)c->b.U, (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, k,
+                         c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  c->ready = true;
+  return GLASMA_OK;
+}
+
+int glasma_step(glasma_ctx* c, int32_t n) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (n < 0) return fail(c, GLASMA_E_ARG, "n must be >= 0");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state: call glasma_init_state or glasma_init_mv first");
+  for (int32_t k = 0; k < n; ++k) {
+    StepConst sc = step_const(c);
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
+                            c->stream);
+      return 0;
+    });
+    c->cur ^= 1;
+    if (sc.hop) {
+      c->offA = (c->offA + 1) % c->g.nz;
+      c->offB = (c->offB + 1) % c->g.nz;
+    }
+    c->step += 1;
+    if (c->p.reunit_every > 0 && c->step % c->p.reunit_every == 0) {
+      dispatch(c, [&]<typename G, typename T>() -> int {
+        launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
+        return 0;
+      });
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+int glasma_reunitarize(glasma_ctx* c) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+int glasma_deposit_current(glasma_ctx* c, void* j_out) {
+  if (!c || !j_out) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  StepConst sc = step_const(c);
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_current<G, T>(cur_U<T>(c), (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, (T*)j_out, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+int glasma_observe(glasma_ctx* c, double* d_out) {
+  if (!c || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  StepConst sc = step_const(c);
+  double* partial = (double*)c->b.work;
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, partial, d_out,
+                         c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+int glasma_observables(glasma_ctx* c, double* tmunu_z, double* gauss_rel, double* gauss_max, double* energy,
+                       double* unitarity_max) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  const size_t nout = 4 * (size_t)c->g.nz + GLASMA_OBS_NSCALARS;
+  double* d_out = (double*)c->b.work + observe_partial_doubles(c->g);
+  int rc = glasma_observe(c, d_out);
+  if (rc) return rc;
+  std::vector<double> h(nout);
+  HIPCHK(c, hipMemcpyAsync(h.data(), d_out, nout * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double* s = h.data() + 4 * c->g.nz;
+  if (tmunu_z) std::memcpy(tmunu_z, h.data(), 4 * c->g.nz * sizeof(double));
+  if (gauss_rel) *gauss_rel = s[GLASMA_OBS_GAUSS_REL];
+  if (gauss_max) *gauss_max = s[GLASMA_OBS_GAUSS_MAX];
+  if (energy) *energy = s[GLASMA_OBS_ENERGY];
+  if (unitarity_max) *unitarity_max = s[GLASMA_OBS_UNITARITY];
+  if (s[GLASMA_OBS_NONFINITE] > 0) return fail(c, GLASMA_E_NONFINITE, "non-finite values in the fields");
+  return GLASMA_OK;
+}
+
+template <typename T>
+static int download(glasma_ctx* c, double* dst, const void* src, size_t n) {
+  std::vector<T> tmp(n);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k < n; ++k) dst[k] = (double)tmp[k];
+  return GLASMA_OK;
+}
+
+int glasma_get_state(glasma_ctx* c, double* U, double* E, double* rhoA, double* rhoB, int64_t* step) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  const size_t V = c->g.V;
+  const int64_t layer = c->g.layer;
+  const int nz = c->g.nz;
+  int rc = dispatch(c, [&]<typename G, typename T>() -> int {
+    int r;
+    if (U && (r = download<T>(c, U, cur_U<T>(c), 3 * (size_t)c->r * V))) return r;
+    if (E && (r = download<T>(c, E, c->b.E, 3 * (size_t)c->ng * V))) return r;
+    std::vector<double> tmp((size_t)c->ng * V);
+    for (int pop = 0; pop < 2; ++pop) {
+      double* dst = pop == 0 ? rhoA : rhoB;
+      if (!dst) continue;
+      if ((r = download<T>(c, tmp.data(), pop == 0 ? c->b.rhoA : c->b.rhoB, tmp.size()))) return r;
+      for (int a = 0; a < c->ng; ++a)
+        for (int z = 0; z < nz; ++z) {
+          int slot = pop == 0 ? slotA(z, c->offA, nz) : slotB(z, c->offB, nz);
+          std::memcpy(dst + (size_t)a * V + (size_t)z * layer, tmp.data() + (size_t)a * V + (size_t)slot * layer,
+                      layer * sizeof(double));
+        }
+    }
+    return GLASMA_OK;
+  });
+  if (rc) return rc;
+  if (step) *step = c->step;
+  return GLASMA_OK;
+}
+
+// ---- host evaluation of the group kernels -----------------------------------
+template <typename G>
+static void host_op(int op, int64_t n, const double* in, double* out) {
+  using T = typename G::Real;
+  constexpr int NG = G::NG, R = G::R;
+  auto rd_link = [](const double* p) {
+    typename G::Link l;
+    T* q = reinterpret_cast<T*>(&l);
+    if constexpr (R == 4) { for (int k = 0; k < 4; ++k) q[k] = (T)p[k]; }
+    else {
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) { l.re[r][k] = (T)p[2 * (3 * r + k)]; l.im[r][k] = (T)p[2 * (3 * r + k) + 1]; }
+    }
+    return l;
+  };
+  auto wr_link = [](const typename G::Link& l, double* p) {
+    const T* q = reinterpret_cast<const T*>(&l);
+    if constexpr (R == 4) { for (int k = 0; k < 4; ++k) p[k] = q[k]; }
+    else {
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) { p[2 * (3 * r + k)] = l.re[r][k]; p[2 * (3 * r + k) + 1] = l.im[r][k]; }
+    }
+  };
+  auto rd_alg = [](const double* p) { typename G::Alg a; for (int k = 0; k < NG; ++k) a.c[k] = (T)p[k]; return a; };
+  auto wr_alg = [](const typename G::Alg& a, double* p) { for (int k = 0; k < NG; ++k) p[k] = a.c[k]; };
+  for (int64_t it = 0; it < n; ++it) {
+    switch (op) {
+      case 0: wr_link(G::expi(rd_alg(in + 1), (T)in[0]), out); in += NG + 1; out += R; break;
+      case 1: wr_alg(G::logi(rd_link(in)), out); in += R; out += NG; break;
+      case 2: wr_alg(G::proj(rd_link(in)), out); in += R; out += NG; break;
+      case 3: wr_alg(G::transport(rd_link(in), rd_alg(in + R)), out); in += R + NG; out += NG; break;
+      case 4: wr_link(G::reunit(rd_link(in)), out); in += R; out += R; break;
+      case 5: out[0] = G::unit_violation(rd_link(in)); in += R; out += 1; break;
+      case 6: wr_link(G::mul(rd_link(in), rd_link(in + R)), out); in += 2 * R; out += R; break;
+    }
+  }
+}
+
+int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const double* in, double* out) {
+  if ((nc != 2 && nc != 3) || (fp != 64 && fp != 32) || op < 0 || op > 6 || n < 0 || (n > 0 && (!in || !out)))
+    return fail(nullptr, GLASMA_E_ARG, "bad arguments to glasma_host_group_op");
+  if (nc == 2 && fp == 64) host_op<Su2<double>>(op, n, in, out);
+  else if (nc == 3 && fp == 64) host_op<Su3<double>>(op, n, in, out);
+  else if (nc == 2) host_op<Su2<float>>(op, n, in, out);
+  else host_op<Su3<float>>(op, n, in, out);
+  return GLASMA_OK;
+}
+

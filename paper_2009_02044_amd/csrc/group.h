@@ -1,0 +1,409 @@
+// SU(2) / SU(3) algebra for the lattice kernels (host + device, templated on the
+// real type T = double or float).
+//
+// Conventions (Sec. 2: the generators t^a are hermitian and traceless):
+//   t^a = sigma^a/2 (SU(2)) or lambda^a/2 (SU(3)), Tr t^a t^b = delta^ab/2.
+//   A Lie-algebra element is stored by its real components X^a = 2 Tr(t^a X).
+//   SU(2) links are unit quaternions U = q0 + i (q1 s1 + q2 s2 + q3 s3); the real
+//   linear span of such matrices is closed under +, * and ^dag, so staple sums use
+//   the same 4-real type.  SU(3) links are full 3x3 complex matrices (18 reals).
+//   proj(M) returns the components of the hermitian traceless part of
+//   (M - M^dag)/(2i); the paper's [M]_ah (Sec. 3, eq. lattice_1) is i proj(M).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#define GL_HD __host__ __device__ __forceinline__
+
+namespace gl {
+
+template <typename T> struct Alg2 { T c[3]; };
+template <typename T> struct Alg3 { T c[8]; };
+
+template <typename T> struct Q2 { T q[4]; };                 // SU(2) span element
+template <typename T> struct M3 { T re[3][3]; T im[3][3]; };  // 3x3 complex
+
+template <typename T> GL_HD T sqr(T x) { return x * x; }
+template <typename T> GL_HD void sincos_r(T x, T* s, T* c);
+template <> GL_HD void sincos_r<double>(double x, double* s, double* c) { sincos(x, s, c); }
+template <> GL_HD void sincos_r<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// ----------------------------------------------------------------------------
+// SU(2)
+// ----------------------------------------------------------------------------
+template <typename T> struct Su2 {
+  static constexpr int NC = 2, NG = 3, R = 4;
+  using Real = T;
+  using Link = Q2<T>;
+  using Alg = Alg2<T>;
+
+  static GL_HD Link zero() { Link r; for (int k = 0; k < 4; ++k) r.q[k] = T(0); return r; }
+  static GL_HD Link one() { Link r = zero(); r.q[0] = T(1); return r; }
+  static GL_HD Alg alg_zero() { Alg r; for (int k = 0; k < 3; ++k) r.c[k] = T(0); return r; }
+
+  // (a0 + i a.s)(b0 + i b.s) = a0 b0 - a.b + i (a0 b + b0 a - a x b).s
+  static GL_HD Link mul(const Link& a, const Link& b) {
+    Link r;
+    r.q[0] = a.q[0] * b.q[0] - a.q[1] * b.q[1] - a.q[2] * b.q[2] - a.q[3] * b.q[3];
+    r.q[1] = a.q[0] * b.q[1] + b.q[0] * a.q[1] - (a.q[2] * b.q[3] - a.q[3] * b.q[2]);
+    r.q[2] = a.q[0] * b.q[2] + b.q[0] * a.q[2] - (a.q[3] * b.q[1] - a.q[1] * b.q[3]);
+    r.q[3] = a.q[0] * b.q[3] + b.q[0] * a.q[3] - (a.q[1] * b.q[2] - a.q[2] * b.q[1]);
+    return r;
+  }
+  static GL_HD Link dag(const Link& a) { Link r; r.q[0] = a.q[0]; r.q[1] = -a.q[1]; r.q[2] = -a.q[2]; r.q[3] = -a.q[3]; return r; }
+  static GL_HD Link mul_dag(const Link& a, const Link& b) { return mul(a, dag(b)); }   // a b^dag
+  static GL_HD Link dag_mul(const Link& a, const Link& b) { return mul(dag(a), b); }   // a^dag b
+  static GL_HD void add_to(Link& acc, const Link& a, T s) { for (int k = 0; k < 4; ++k) acc.q[k] += s * a.q[k]; }
+  // (U - U^dag)/(2i) = q.s  ->  components 2 q_a
+  static GL_HD Alg proj(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
+  static GL_HD T retr(const Link& m) { return 2 * m.q[0]; }               // Re Tr
+  // exp(i s X), X = x.s/2: cos(|sx|/2) + i sin(|sx|/2) n.s
+  static GL_HD Link expi(const Alg& x, T s) {
+    T v0 = s * x.c[0], v1 = s * x.c[1], v2 = s * x.c[2];
+    T th2 = v0 * v0 + v1 * v1 + v2 * v2;
+    T th = sqrt(th2);
+    T h = th * T(0.5);
+    T sn, cs;
+    sincos_r<T>(h, &sn, &cs);
+    // sin(h)/th = sin(h)/(2h) with a series near 0
+    T f = (h < T(1e-3)) ? T(0.5) * (T(1) - h * h / T(6) * (T(1) - h * h / T(20)))
+                        : sn / th;
+    Link r; r.q[0] = cs; r.q[1] = f * v0; r.q[2] = f * v1; r.q[3] = f * v2;
+    return r;
+  }
+  // pure quaternion i X = (0, x/2)
+  static GL_HD Link alg_as_link(const Alg& x) { Link r; r.q[0] = 0; r.q[1] = x.c[0] / 2; r.q[2] = x.c[1] / 2; r.q[3] = x.c[2] / 2; return r; }
+  static GL_HD Alg link_as_alg(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
+  // U^dag X U
+  static GL_HD Alg transport(const Link& u, const Alg& x) { return link_as_alg(mul(dag_mul(u, alg_as_link(x)), u)); }
+  // U X U^dag
+  static GL_HD Alg transport_inv(const Link& u, const Alg& x) { return link_as_alg(mul_dag(mul(u, alg_as_link(x)), u)); }
+  // principal -i Log W (closed form): W = cos(th/2) + i sin(th/2) n.s -> th n
+  static GL_HD Alg logi(const Link& w) {
+    T s2 = w.q[1] * w.q[1] + w.q[2] * w.q[2] + w.q[3] * w.q[3];
+    T s = sqrt(s2);
+    T th = T(2) * atan2(s, w.q[0]);
+    T f = (s < T(1e-300)) ? T(2) : th / s;
+    Alg r; r.c[0] = f * w.q[1]; r.c[1] = f * w.q[2]; r.c[2] = f * w.q[3];
+    return r;
+  }
+  static GL_HD Link reunit(const Link& m) {
+    T n = sqrt(m.q[0] * m.q[0] + m.q[1] * m.q[1] + m.q[2] * m.q[2] + m.q[3] * m.q[3]);
+    Link r; for (int k = 0; k < 4; ++k) r.q[k] = m.q[k] / n; return r;
+  }
+  // max |U^dag U - 1| and |det U - 1| for a unit quaternion: | |q|^2 - 1 |
+  static GL_HD T unit_violation(const Link& m) {
+    T n = m.q[0] * m.q[0] + m.q[1] * m.q[1] + m.q[2] * m.q[2] + m.q[3] * m.q[3];
+    return fabs(n - T(1));
+  }
+};
+
+// ----------------------------------------------------------------------------
+// SU(3)
+// ----------------------------------------------------------------------------
+
+template <typename T> struct Su3 {
+  static constexpr int NC = 3, NG = 8, R = 18;
+  using Real = T;
+  using Link = M3<T>;
+  using Alg = Alg3<T>;
+
+  static GL_HD Link zero() {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { r.re[i][j] = T(0); r.im[i][j] = T(0); }
+    return r;
+  }
+  static GL_HD Link one() { Link r = zero(); r.re[0][0] = r.re[1][1] = r.re[2][2] = T(1); return r; }
+  static GL_HD Alg alg_zero() { Alg r; for (int k = 0; k < 8; ++k) r.c[k] = T(0); return r; }
+
+  static GL_HD Link mul(const Link& a, const Link& b) {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = a.re[i][0] * b.re[0][j] - a.im[i][0] * b.im[0][j];
+        T si = a.re[i][0] * b.im[0][j] + a.im[i][0] * b.re[0][j];
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+          sr += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
+          si += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+        }
+        r.re[i][j] = sr; r.im[i][j] = si;
+      }
+    return r;
+  }
+  // a b^dag: (a b^dag)_ij = sum_k a_ik conj(b_jk)
+  static GL_HD Link mul_dag(const Link& a, const Link& b) {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = a.re[i][0] * b.re[j][0] + a.im[i][0] * b.im[j][0];
+        T si = a.im[i][0] * b.re[j][0] - a.re[i][0] * b.im[j][0];
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+          sr += a.re[i][k] * b.re[j][k] + a.im[i][k] * b.im[j][k];
+          si += a.im[i][k] * b.re[j][k] - a.re[i][k] * b.im[j][k];
+        }
+        r.re[i][j] = sr; r.im[i][j] = si;
+      }
+    return r;
+  }
+  // a^dag b: sum_k conj(a_ki) b_kj
+  static GL_HD Link dag_mul(const Link& a, const Link& b) {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = a.re[0][i] * b.re[0][j] + a.im[0][i] * b.im[0][j];
+        T si = a.re[0][i] * b.im[0][j] - a.im[0][i] * b.re[0][j];
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+          sr += a.re[k][i] * b.re[k][j] + a.im[k][i] * b.im[k][j];
+          si += a.re[k][i] * b.im[k][j] - a.im[k][i] * b.re[k][j];
+        }
+        r.re[i][j] = sr; r.im[i][j] = si;
+      }
+    return r;
+  }
+  static GL_HD Link dag(const Link& a) {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { r.re[i][j] = a.re[j][i]; r.im[i][j] = -a.im[j][i]; }
+    return r;
+  }
+  static GL_HD void add_to(Link& acc, const Link& a, T s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { acc.re[i][j] += s * a.re[i][j]; acc.im[i][j] += s * a.im[i][j]; }
+  }
+  // components of the hermitian traceless part of (M - M^dag)/(2i), X^a = Tr(lambda^a A)
+  static GL_HD Alg proj(const Link& m) {
+    const T is3 = T(0.57735026918962576451);
+    Alg r;
+    r.c[0] = m.im[0][1] + m.im[1][0];
+    r.c[1] = m.re[0][1] - m.re[1][0];
+    r.c[2] = m.im[0][0] - m.im[1][1];
+    r.c[3] = m.im[0][2] + m.im[2][0];
+    r.c[4] = m.re[0][2] - m.re[2][0];
+    r.c[5] = m.im[1][2] + m.im[2][1];
+    r.c[6] = m.re[1][2] - m.re[2][1];
+    r.c[7] = (m.im[0][0] + m.im[1][1] - T(2) * m.im[2][2]) * is3;
+    return r;
+  }
+  static GL_HD T retr(const Link& m) { return m.re[0][0] + m.re[1][1] + m.re[2][2]; }
+  // hermitian matrix X = sum_a x^a lambda^a / 2, scaled by s
+  static GL_HD Link herm(const Alg& x, T s) {
+    const T is3 = T(0.57735026918962576451);
+    T h = s * T(0.5);
+    Link q;
+    q.re[0][0] = h * (x.c[2] + x.c[7] * is3); q.im[0][0] = 0;
+    q.re[1][1] = h * (-x.c[2] + x.c[7] * is3); q.im[1][1] = 0;
+    q.re[2][2] = -h * T(2) * x.c[7] * is3; q.im[2][2] = 0;
+    q.re[0][1] = h * x.c[0]; q.im[0][1] = -h * x.c[1];
+    q.re[1][0] = h * x.c[0]; q.im[1][0] = h * x.c[1];
+    q.re[0][2] = h * x.c[3]; q.im[0][2] = -h * x.c[4];
+    q.re[2][0] = h * x.c[3]; q.im[2][0] = h * x.c[4];
+    q.re[1][2] = h * x.c[5]; q.im[1][2] = -h * x.c[6];
+    q.re[2][1] = h * x.c[5]; q.im[2][1] = h * x.c[6];
+    return q;
+  }
+  // components of a hermitian traceless matrix
+  static GL_HD Alg alg_of_herm(const Link& q) {
+    const T is3 = T(0.57735026918962576451);
+    Alg r;
+    r.c[0] = q.re[0][1] + q.re[1][0];
+    r.c[1] = -q.im[0][1] + q.im[1][0];
+    r.c[2] = q.re[0][0] - q.re[1][1];
+    r.c[3] = q.re[0][2] + q.re[2][0];
+    r.c[4] = -q.im[0][2] + q.im[2][0];
+    r.c[5] = q.re[1][2] + q.re[2][1];
+    r.c[6] = -q.im[1][2] + q.im[2][1];
+    r.c[7] = (q.re[0][0] + q.re[1][1] - T(2) * q.re[2][2]) * is3;
+    return r;
+  }
+
+  // exp(i Q), Q = s x^a t^a hermitian traceless, by the Cayley-Hamilton closed form of
+  // Morningstar & Peardon, Phys. Rev. D 69, 054501 (2004): exp(iQ) = f0 + f1 Q + f2 Q^2
+  // with c0 = det Q, c1 = Tr Q^2 / 2, eigenvalues 2u, -u +- w.  For tiny c1 the
+  // power series of exp is summed with Q^3 = c1 Q + c0 reducing every power.
+  static GL_HD Link expi(const Alg& x, T s) {
+    Link Q = herm(x, s);
+    Link Q2 = mul(Q, Q);
+    T c1 = T(0.5) * (Q2.re[0][0] + Q2.re[1][1] + Q2.re[2][2]);
+    // det Q = Tr(Q^3)/3 for traceless Q
+    T trq3 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) trq3 += Q.re[i][k] * Q2.re[k][i] - Q.im[i][k] * Q2.im[k][i];
+    T c0 = trq3 / T(3);
+    T f0r, f0i, f1r, f1i, f2r, f2i;
+    const T small = sizeof(T) == 8 ? T(1e-6) : T(1e-3);
+    if (c1 < small) {
+      // sum_n (i^n/n!) Q^n with Q^n = a_n + b_n Q + c_n Q^2
+      T a = 1, b = 0, c = 0;             // Q^0
+      f0r = 1; f0i = 0; f1r = 0; f1i = 0; f2r = 0; f2i = 0;
+      T fact = 1;
+      const int nterm = sizeof(T) == 8 ? 14 : 9;
+      for (int n = 1; n <= nterm; ++n) {
+        T an = c0 * c, bn = a + c1 * c, cn = b;
+        a = an; b = bn; c = cn;
+        fact *= T(n);
+        T w = T(1) / fact;
+        int ph = n & 3;               // i^n = 1, i, -1, -i
+        T wr = (ph == 0) ? w : (ph == 2 ? -w : T(0));
+        T wi = (ph == 1) ? w : (ph == 3 ? -w : T(0));
+        f0r += wr * a; f0i += wi * a;
+        f1r += wr * b; f1i += wi * b;
+        f2r += wr * c; f2i += wi * c;
+      }
+    } else {
+      bool neg = c0 < T(0);
+      T c0a = neg ? -c0 : c0;
+      T sq = sqrt(c1 / T(3));
+      T c0max = T(2) * sq * sq * sq;
+      T r = c0a / c0max;
+      r = r > T(1) ? T(1) : r;
+      T theta = acos(r);
+      T st, ct;
+      sincos_r<T>(theta / T(3), &st, &ct);
+      T u = sq * ct;
+      T w = sqrt(c1) * st;
+      T u2 = u * u, w2 = w * w;
+      T sw, cw;
+      sincos_r<T>(w, &sw, &cw);
+      T xi0 = (fabs(w) < T(0.05)) ? T(1) - w2 / T(6) * (T(1) - w2 / T(20) * (T(1) - w2 / T(42))) : sw / w;
+      T s2u, c2u, su, cu;
+      sincos_r<T>(T(2) * u, &s2u, &c2u);
+      sincos_r<T>(u, &su, &cu);
+      // e^{-iu} = cu - i su
+      // h0 = (u2 - w2) e^{2iu} + e^{-iu} (8 u2 cw + 2 i u (3 u2 + w2) xi0)
+      T br = T(8) * u2 * cw, bi = T(2) * u * (T(3) * u2 + w2) * xi0;
+      T h0r = (u2 - w2) * c2u + (cu * br + su * bi);
+      T h0i = (u2 - w2) * s2u + (cu * bi - su * br);
+      // h1 = 2u e^{2iu} - e^{-iu} (2u cw - i (3u2 - w2) xi0)
+      br = T(2) * u * cw; bi = -(T(3) * u2 - w2) * xi0;
+      T h1r = T(2) * u * c2u - (cu * br + su * bi);
+      T h1i = T(2) * u * s2u - (cu * bi - su * br);
+      // h2 = e^{2iu} - e^{-iu} (cw + 3 i u xi0)
+      br = cw; bi = T(3) * u * xi0;
+      T h2r = c2u - (cu * br + su * bi);
+      T h2i = s2u - (cu * bi - su * br);
+      T inv = T(1) / (T(9) * u2 - w2);
+      f0r = h0r * inv; f0i = h0i * inv;
+      f1r = h1r * inv; f1i = h1i * inv;
+      f2r = h2r * inv; f2i = h2i * inv;
+      if (neg) {  // f_j(-c0) = (-1)^j conj(f_j(c0))
+        f0i = -f0i;
+        f1r = -f1r;
+        f2i = -f2i;
+      }
+    }
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T qr = Q.re[i][j], qi = Q.im[i][j], pr = Q2.re[i][j], pi = Q2.im[i][j];
+        r.re[i][j] = f1r * qr - f1i * qi + f2r * pr - f2i * pi;
+        r.im[i][j] = f1r * qi + f1i * qr + f2r * pi + f2i * pr;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { r.re[i][i] += f0r; r.im[i][i] += f0i; }
+    return r;
+  }
+  // U^dag X U
+  static GL_HD Alg transport(const Link& u, const Alg& x) {
+    Link X = herm(x, T(1));
+    return alg_of_herm(mul(dag_mul(u, X), u));
+  }
+  // U X U^dag
+  static GL_HD Alg transport_inv(const Link& u, const Alg& x) {
+    Link X = herm(x, T(1));
+    return alg_of_herm(mul_dag(mul(u, X), u));
+  }
+  // principal -i Log W for W close to 1 (all eigen-angles well inside (-pi/2, pi/2)):
+  // fixed point of H <- H + proj(exp(-iH/2) W exp(-iH/2)), which converges with the
+  // cube of the symmetric-splitting error; at the fixed point W = exp(iH).
+  static GL_HD Alg logi(const Link& w) {
+    Alg h = proj(w);
+    for (int it = 0; it < 40; ++it) {
+      Link hm = expi(h, T(-0.5));
+      Link R = mul(mul(hm, w), hm);
+      Alg d = proj(R);
+      T n = T(0);
+      for (int k = 0; k < 8; ++k) { h.c[k] += d.c[k]; n += d.c[k] * d.c[k]; }
+      if (n < (sizeof(T) == 8 ? T(1e-30) : T(1e-14))) break;
+    }
+    return h;
+  }
+  // rows 1, 2 Gram-Schmidt, row 3 = conj(r1 x r2)
+  static GL_HD Link reunit(const Link& m) {
+    Link r = m;
+    T n0 = T(0);
+    for (int k = 0; k < 3; ++k) n0 += r.re[0][k] * r.re[0][k] + r.im[0][k] * r.im[0][k];
+    n0 = T(1) / sqrt(n0);
+    for (int k = 0; k < 3; ++k) { r.re[0][k] *= n0; r.im[0][k] *= n0; }
+    // r1 -= (r0^* . r1) r0
+    T pr = 0, pi = 0;
+    for (int k = 0; k < 3; ++k) {
+      pr += r.re[0][k] * r.re[1][k] + r.im[0][k] * r.im[1][k];
+      pi += r.re[0][k] * r.im[1][k] - r.im[0][k] * r.re[1][k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      r.re[1][k] -= pr * r.re[0][k] - pi * r.im[0][k];
+      r.im[1][k] -= pr * r.im[0][k] + pi * r.re[0][k];
+    }
+    T n1 = T(0);
+    for (int k = 0; k < 3; ++k) n1 += r.re[1][k] * r.re[1][k] + r.im[1][k] * r.im[1][k];
+    n1 = T(1) / sqrt(n1);
+    for (int k = 0; k < 3; ++k) { r.re[1][k] *= n1; r.im[1][k] *= n1; }
+    // r2 = conj(r0 x r1)
+    for (int k = 0; k < 3; ++k) {
+      int a = (k + 1) % 3, b = (k + 2) % 3;
+      T cr = r.re[0][a] * r.re[1][b] - r.im[0][a] * r.im[1][b] - (r.re[0][b] * r.re[1][a] - r.im[0][b] * r.im[1][a]);
+      T ci = r.re[0][a] * r.im[1][b] + r.im[0][a] * r.re[1][b] - (r.re[0][b] * r.im[1][a] + r.im[0][b] * r.re[1][a]);
+      r.re[2][k] = cr; r.im[2][k] = -ci;
+    }
+    return r;
+  }
+  // max |U^dag U - 1|_entry and |det U - 1|
+  static GL_HD T unit_violation(const Link& m) {
+    Link p = dag_mul(m, m);
+    T v = T(0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        T d = fabs(p.re[i][j] - (i == j ? T(1) : T(0)));
+        T e = fabs(p.im[i][j]);
+        v = d > v ? d : v; v = e > v ? e : v;
+      }
+    // det
+    T dr = 0, di = 0;
+    for (int k = 0; k < 3; ++k) {
+      int a = (k + 1) % 3, b = (k + 2) % 3;
+      // cofactor of (0,k): m1a m2b - m1b m2a
+      T cr = m.re[1][a] * m.re[2][b] - m.im[1][a] * m.im[2][b] - (m.re[1][b] * m.re[2][a] - m.im[1][b] * m.im[2][a]);
+      T ci = m.re[1][a] * m.im[2][b] + m.im[1][a] * m.re[2][b] - (m.re[1][b] * m.im[2][a] + m.im[1][b] * m.re[2][a]);
+      dr += m.re[0][k] * cr - m.im[0][k] * ci;
+      di += m.re[0][k] * ci + m.im[0][k] * cr;
+    }
+    T dd = sqrt((dr - 1) * (dr - 1) + di * di);
+    return dd > v ? dd : v;
+  }
+};
+
+template <int NC, typename T> struct GroupOf;
+template <typename T> struct GroupOf<2, T> { using type = Su2<T>; };
+template <typename T> struct GroupOf<3, T> { using type = Su3<T>; };
+
+}  // namespace gl

@@ -1,0 +1,180 @@
+// Initial conditions of two MV nuclei with finite longitudinal extent, computed on
+// the GPU in double precision (Sec. 2: Gaussian W[rho] and the Fourier solution of
+// the transverse Poisson equation with IR regulator m and UV cutoff Lambda;
+// Sec. 3: eqs. single_sheet, 3d_colorfield_1, 3d_colorfield_2, the temporal gauge,
+// and the CPIC charges that satisfy eq. gauss).
+//
+// 1. phi^a_N = DFT^-1[ rho~^a_N Theta(Lambda - |k~|) / (k~^2 + m^2) ] on the nt x nt
+//    transverse torus, k~^2 = (2/a_T)^2 (sin^2(pi kx/nt) + sin^2(pi ky/nt)), by four
+//    separable direct DFT passes (nt <= a few hundred, one-shot per event).
+// 2. Wilson lines V_N(x, t) = exp(-i Lambda_N(z, t) phi_N(x_T)): the colour structure
+//    of a single sheet does not depend on z, so the path ordering is trivial and the
+//    cumulative normalised Gaussian profile is
+//      Lambda_B = erfc((z - z_B - (t - t0)) / (sqrt 2 sigma)) / 2   (B moves +z),
+//      Lambda_A = erfc(-(z - z_A + (t - t0)) / (sqrt 2 sigma)) / 2  (A moves -z).
+// 3. U_i = [V_A(x) V_A^dag(x+i)] [V_B(x) V_B^dag(x+i)] (i = x, y), U_z = 1 except the
+//    periodic seam U_z(x_T, nz-1) = V_A(x_T, nz-1) V_B^dag(x_T, 0), at t0 and t0 - dt.
+// 4. E_i(t0 - dt/2) = -i Log(U_i(t0) U_i^dag(t0 - dt)) / (a_i dt), principal Log.
+// 5. rho = sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)] / a_i at U(t0); layers
+//    z < nz/2 go to nucleus B, the others to nucleus A.
+#include "internal.h"
+
+namespace gl {
+
+size_t ic_work_doubles(const Geom& g, int ng) { return (size_t)6 * 2 * ng * g.layer; }
+
+__global__ void k_dft(const double* __restrict__ in, double* __restrict__ out, int nt, int nb, int mode,
+                      double a_T, double m_ir, double uv_cut) {
+  const int64_t n2 = (int64_t)nt * nt;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nb * n2) return;
+  const int b = (int)(tid / n2);
+  const int y = (int)((tid / nt) % nt);
+  const int x = (int)(tid % nt);
+  const double* ib = in + (mode == 0 ? 1 : 2) * (int64_t)b * n2;
+  double sr = 0.0, si = 0.0;
+  if (mode == 0) {          // real in, forward along x: out[b][y][kx=x]
+    for (int u = 0; u < nt; ++u) {
+      double s, c;
+      sincospi(2.0 * (double)((x * u) % nt) / nt, &s, &c);
+      double v = ib[(int64_t)y * nt + u];
+      sr += v * c; si -= v * s;
+    }
+  } else if (mode == 1 || mode == 2) {   // along y: out[b][ky=y][kx=x]
+    const double sg = mode == 1 ? -1.0 : 1.0;
+    for (int u = 0; u < nt; ++u) {
+      double s, c;
+      sincospi(2.0 * (double)((y * u) % nt) / nt, &s, &c);
+      s *= sg;
+      double vr = ib[2 * ((int64_t)u * nt + x)], vi = ib[2 * ((int64_t)u * nt + x) + 1];
+      sr += vr * c - vi * s; si += vr * s + vi * c;
+    }
+    if (mode == 1) {
+      double sy = sinpi((double)y / nt), sx = sinpi((double)x / nt);
+      double k2 = (2.0 / a_T) * (2.0 / a_T) * (sy * sy + sx * sx);
+      double f = 1.0 / (k2 + m_ir * m_ir);
+      if (uv_cut > 0.0 && sqrt(k2) > uv_cut) f = 0.0;
+      sr *= f; si *= f;
+    }
+  } else {                  // complex in, inverse along x, real out / nt^2
+    for (int u = 0; u < nt; ++u) {
+      double s, c;
+      sincospi(2.0 * (double)((x * u) % nt) / nt, &s, &c);
+      double vr = ib[2 * ((int64_t)y * nt + u)], vi = ib[2 * ((int64_t)y * nt + u) + 1];
+      sr += vr * c - vi * s;
+    }
+    out[tid] = sr / (double)n2;
+    return;
+  }
+  out[2 * tid] = sr;
+  out[2 * tid + 1] = si;
+}
+
+template <typename Gd>
+__device__ __forceinline__ typename Gd::Link wilson(const double* __restrict__ phi, int nucleus, int64_t t,
+                                                    int64_t layer, double lam) {
+  typename Gd::Alg p;
+  constexpr int NG = Gd::NG;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) p.c[k] = phi[((int64_t)nucleus * NG + k) * layer + t];
+  return Gd::expi(p, -lam);
+}
+
+__device__ __forceinline__ double profileA(double z, double tau, const McvConst& mv) {
+  return 0.5 * erfc(-(z - mv.zA + tau) / (1.4142135623730951 * mv.sigma));
+}
+__device__ __forceinline__ double profileB(double z, double tau, const McvConst& mv) {
+  return 0.5 * erfc((z - mv.zB - tau) / (1.4142135623730951 * mv.sigma));
+}
+
+template <typename Gd>
+__device__ typename Gd::Link ic_link(const double* __restrict__ phi, const Geom& g, int x, int y, int z, int i,
+                                     double tau, double a_L, const McvConst& mv) {
+  using L = typename Gd::Link;
+  const int64_t t = (int64_t)y * g.nt + x;
+  if (i == 2) {
+    if (z != g.nz - 1) return Gd::one();
+    L VA = wilson<Gd>(phi, 0, t, g.layer, profileA((g.nz - 1) * a_L, tau, mv));
+    L VB = wilson<Gd>(phi, 1, t, g.layer, profileB(0.0, tau, mv));
+    return Gd::mul_dag(VA, VB);
+  }
+  const int xp = i == 0 ? wrap_add(x, 1, g.nt) : x;
+  const int yp = i == 1 ? wrap_add(y, 1, g.nt) : y;
+  const int64_t tp = (int64_t)yp * g.nt + xp;
+  const double zz = z * a_L;
+  const double lA = profileA(zz, tau, mv), lB = profileB(zz, tau, mv);
+  L UA = Gd::mul_dag(wilson<Gd>(phi, 0, t, g.layer, lA), wilson<Gd>(phi, 0, tp, g.layer, lA));
+  L UB = Gd::mul_dag(wilson<Gd>(phi, 1, t, g.layer, lB), wilson<Gd>(phi, 1, tp, g.layer, lB));
+  return Gd::mul(UA, UB);
+}
+
+template <typename Gd, typename T>
+__global__ void k_ic_links(const double* __restrict__ phi, T* __restrict__ U, T* __restrict__ E, Geom g,
+                           StepConst c, McvConst mv) {
+  constexpr int NG = Gd::NG;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int x = (int)(s % g.nt), y = (int)((s / g.nt) % g.nt), z = (int)(s / g.layer);
+  for (int i = 0; i < 3; ++i) {
+    typename Gd::Link U0 = ic_link<Gd>(phi, g, x, y, z, i, 0.0, c.a[2], mv);
+    typename Gd::Link U1 = ic_link<Gd>(phi, g, x, y, z, i, -c.dt, c.a[2], mv);
+    typename Gd::Alg e = Gd::logi(Gd::mul_dag(U0, U1));
+    const double k = 1.0 / (c.a[i] * c.dt);
+    for (int q = 0; q < NG; ++q) e.c[q] *= k;
+    store_link(U0, U, i, s, g.V);
+    store_alg(e, E + (int64_t)i * NG * g.V, s, g.V);
+  }
+}
+
+template <typename Gd, typename T>
+__global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, T* __restrict__ rhoA,
+                           T* __restrict__ rhoB, Geom g, StepConst c) {
+  constexpr int NG = Gd::NG;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int64_t V = g.V;
+  Site x;
+  x.x = (int)(s % g.nt); x.y = (int)((s / g.nt) % g.nt); x.z = (int)(s / g.layer);
+  typename Gd::Alg r = Gd::alg_zero();
+  for (int i = 0; i < 3; ++i) {
+    const int64_t sm = idx(g, shifted(g, x, i, -1));
+    typename Gd::Link Um;
+    load_link(Um, U, i, sm, V);
+    typename Gd::Alg eh, em;
+    load_alg(eh, E + (int64_t)i * NG * V, s, V);
+    load_alg(em, E + (int64_t)i * NG * V, sm, V);
+    typename Gd::Alg tr = Gd::transport(Um, em);
+    for (int q = 0; q < NG; ++q) r.c[q] += (eh.c[q] - tr.c[q]) / c.a[i];
+  }
+  typename Gd::Alg zero = Gd::alg_zero();
+  const bool isB = x.z < g.nz / 2;
+  store_alg(isB ? r : zero, rhoB, s, V);
+  store_alg(isB ? zero : r, rhoA, s, V);
+}
+
+template <typename G, typename T>
+void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T* rhoB, const Geom& g,
+                    const StepConst& c, const McvConst& mv, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int nb = 2 * G::NG;
+  const int64_t m = (int64_t)nb * g.layer;
+  double* phi = work + m;
+  double* c1 = work + 2 * m;
+  double* c2 = work + 4 * m;
+  const int bs = 256;
+  const unsigned gb = (unsigned)((m + bs - 1) / bs);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, rhoT_dev, c1, g.nt, nb, 0, c.a[0], mv.m_ir, mv.uv_cut);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, c2, g.nt, nb, 1, c.a[0], mv.m_ir, mv.uv_cut);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c2, c1, g.nt, nb, 2, c.a[0], mv.m_ir, mv.uv_cut);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, phi, g.nt, nb, 3, c.a[0], mv.m_ir, mv.uv_cut);
+  const unsigned sb = (unsigned)((g.V + bs - 1) / bs);
+  hipLaunchKernelGGL((k_ic_links<Gd, T>), dim3(sb), dim3(bs), 0, st, phi, U, E, g, c, mv);
+  hipLaunchKernelGGL((k_ic_gauss<Gd, T>), dim3(sb), dim3(bs), 0, st, U, E, rhoA, rhoB, g, c);
+}
+
+template void launch_init_mv<Su2<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
+template void launch_init_mv<Su3<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
+template void launch_init_mv<Su2<float>, float>(const double*, double*, float*, float*, float*, float*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
+template void launch_init_mv<Su3<float>, float>(const double*, double*, float*, float*, float*, float*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
+
+}  // namespace gl

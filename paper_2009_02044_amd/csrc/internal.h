@@ -1,0 +1,41 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "lattice.h"
+
+namespace gl {
+
+template <typename G, typename T>
+void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
+                     hipStream_t st);
+
+// Observables at the current integer time, written to `out` (device, double):
+// [0, 4 nz): transverse means eps, p_L, p_T, S_L per layer; then OBS_* scalars.
+enum {
+  OBS_ENERGY = 0, OBS_GAUSS_L2, OBS_RHO_L2, OBS_GAUSS_MAX, OBS_UNITARITY, OBS_NONFINITE,
+  OBS_GAUSS_REL, OBS_NSCALARS = 8
+};
+template <typename G, typename T>
+void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
+                    const StepConst& c, double* partial, double* out, hipStream_t st);
+size_t observe_partial_doubles(const Geom& g);
+
+template <typename G, typename T>
+void launch_current(const T* U, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c,
+                    T* j, hipStream_t st);
+
+template <typename G, typename T>
+void launch_reunit(T* U, const Geom& g, hipStream_t st);
+
+// Initial conditions: rhoT_dev holds the transverse charges of both nuclei
+// (double, [2][NG][nt*nt]: A then B); work needs ic_work_doubles(g, NG) doubles.
+struct McvConst {
+  double m_ir, uv_cut, sigma, zA, zB;
+};
+size_t ic_work_doubles(const Geom& g, int ng);
+template <typename G, typename T>
+void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T* rhoB,
+                    const Geom& g, const StepConst& c, const McvConst& mv, hipStream_t st);
+
+}  // namespace gl

@@ -1,0 +1,265 @@
+// Observables (Sec. 4: <T^{mu nu}> components and eq. pT_eL; Sec. 3: eq. gauss),
+// the CPIC current of the next step, and FP64 reunitarisation of the links.
+//
+// At integer time t (state U(t), E(t - dt/2), rho(t - dt/2)) every thread recomputes
+// the E update of its site in double precision without applying it, then forms
+//   E_i^2 = (|E_i(t-dt/2)|^2 + |E_i(t+dt/2)|^2)/2,
+//   B_ij^2 = 4/(a_i a_j)^2 Re Tr(1 - U_{i,j}),  F_ij^a = proj(U_{i,j})^a / (a_i a_j),
+//   eps = (E^2 + B^2)/2, p_T = (E_L^2 + B_L^2)/2, p_L = (E_T^2 + B_T^2 - E_L^2 - B_L^2)/2,
+//   S_L = -sum_a (Ebar_x^a F_zx^a - Ebar_y^a F_yz^a),  Ebar = (E(t-dt/2) + E(t+dt/2))/2,
+// (E = d_t A is minus the physical field, hence the sign of S_L), the Gauss residual
+//   G(x) = sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)]/a_i - rho(x),
+// link unitarity and a non-finite count.  A block covers part of one z layer; its
+// partial sums land in a fixed slot and a single-block pass adds them in a fixed
+// order, so results are bitwise reproducible.
+#include "internal.h"
+#include "stencil.h"
+
+namespace gl {
+
+constexpr int NQ = 9;   // eps, pL, pT, SL, |G|^2, |rho|^2, max|G^a|, max unitarity, nonfinite
+constexpr int OBS_BS = 256;
+
+static int obs_blocks_per_layer(const Geom& g) {
+  int64_t nb = (g.layer + OBS_BS - 1) / OBS_BS;
+  return (int)(nb < 16 ? nb : 16);
+}
+size_t observe_partial_doubles(const Geom& g) {
+  return (size_t)obs_blocks_per_layer(g) * g.nz * NQ;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+template <typename A> __device__ __forceinline__ double norm2(const A& a) {
+  constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
+  double s = 0;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) s += (double)a.c[k] * (double)a.c[k];
+  return s;
+}
+
+template <typename G, typename T>
+__global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, const T* __restrict__ E,
+                                                    const T* __restrict__ rhoA, const T* __restrict__ rhoB,
+                                                    Geom g, StepConst c, double* __restrict__ partial) {
+  using L = typename G::Link;   // double precision group
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t V = g.V;
+  const int z = blockIdx.y;
+  const int nbx = gridDim.x;
+  const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * OBS_BS + threadIdx.x; t < g.layer; t += (int64_t)nbx * OBS_BS) {
+    const int64_t s = (int64_t)z * g.layer + t;
+    Site x;
+    x.x = (int)(t % g.nt);
+    x.y = (int)(t / g.nt);
+    x.z = z;
+    double e2[3];
+    A ebar[2];
+    bool bad = false;
+    for (int i = 0; i < 3; ++i) {
+      L S = staple_sum<G, T>(U, g, x, i, inv_a2);
+      L Ui;
+      load_link(Ui, U, i, s, V);
+      A f = G::proj(G::mul(Ui, S));
+      A eo, en;
+      load_alg(eo, E + (int64_t)i * NG * V, s, V);
+      for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k] - c.dt / c.a[i] * f.c[k];
+      if (c.hop && i == 2) {
+        A rb, ra;
+        load_alg(rb, rhoB, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), V);
+        load_alg(ra, rhoA, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), V);
+        A ran = G::transport_inv(Ui, ra);
+        for (int k = 0; k < NG; ++k) en.c[k] += c.a[2] * (ran.c[k] - rb.c[k]);
+      }
+      for (int k = 0; k < NG; ++k) bad |= !isfinite(en.c[k]);
+      e2[i] = 0.5 * (norm2(eo) + norm2(en));
+      if (i < 2)
+        for (int k = 0; k < NG; ++k) ebar[i].c[k] = 0.5 * (eo.c[k] + en.c[k]);
+      double uv = G::unit_violation(Ui);
+      bad |= !isfinite(uv);
+      acc[7] = fmax(acc[7], uv);
+    }
+    const double nc = (double)G::NC;
+    L Pxy = plaquette<G, T>(U, g, x, 0, 1);
+    L Pyz = plaquette<G, T>(U, g, x, 1, 2);
+    L Pzx = plaquette<G, T>(U, g, x, 2, 0);
+    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - G::retr(Pxy));
+    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - G::retr(Pyz));
+    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - G::retr(Pzx));
+    A Fyz = G::proj(Pyz), Fzx = G::proj(Pzx);
+    const double kyz = 1.0 / (c.a[1] * c.a[2]), kzx = 1.0 / (c.a[2] * c.a[0]);
+    double sl = 0.0;
+    for (int k = 0; k < NG; ++k) sl -= ebar[0].c[k] * Fzx.c[k] * kzx - ebar[1].c[k] * Fyz.c[k] * kyz;
+    const double EL2 = e2[2], ET2 = e2[0] + e2[1], BL2 = bxy, BT2 = byz + bzx;
+    acc[0] += 0.5 * (EL2 + ET2 + BL2 + BT2);
+    acc[1] += 0.5 * (ET2 + BT2 - EL2 - BL2);
+    acc[2] += 0.5 * (EL2 + BL2);
+    acc[3] += sl;
+    // Gauss residual at (U(t), E(t - dt/2), rho(t - dt/2))
+    A G_, r, rb;
+    load_alg(r, rhoA, site_index(g, x.x, x.y, slotA(z, c.offA, g.nz)), V);
+    load_alg(rb, rhoB, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), V);
+    for (int k = 0; k < NG; ++k) { r.c[k] += rb.c[k]; G_.c[k] = -r.c[k]; }
+    for (int i = 0; i < 3; ++i) {
+      Site xm = shifted(g, x, i, -1);
+      const int64_t sm = idx(g, xm);
+      L Um;
+      load_link(Um, U, i, sm, V);
+      A eh, em;
+      load_alg(eh, E + (int64_t)i * NG * V, s, V);
+      load_alg(em, E + (int64_t)i * NG * V, sm, V);
+      A tr = G::transport(Um, em);
+      for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tr.c[k]) / c.a[i];
+    }
+    acc[4] += norm2(G_);
+    acc[5] += norm2(r);
+    double gm = 0.0;
+    for (int k = 0; k < NG; ++k) gm = fmax(gm, fabs(G_.c[k]));
+    acc[6] = fmax(acc[6], gm);
+    bad |= !isfinite(acc[0]) || !isfinite(acc[4]);
+    acc[8] += bad ? 1.0 : 0.0;
+  }
+  // block reduction: 64-lane shuffles, then across the waves through LDS
+  __shared__ double red[OBS_BS / 64][NQ];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double v = (q == 6 || q == 7) ? wave_max(acc[q]) : wave_sum(acc[q]);
+    if (lane == 0) red[wv][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    double v = red[0][q];
+    for (int w = 1; w < OBS_BS / 64; ++w) v = (q == 6 || q == 7) ? fmax(v, red[w][q]) : v + red[w][q];
+    partial[((int64_t)z * nbx + blockIdx.x) * NQ + q] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_observe_finish(const double* __restrict__ partial, int nbx, Geom g,
+                                                        StepConst c, double* __restrict__ out) {
+  const int nz = g.nz;
+  double loc[NQ];
+  for (int q = 0; q < NQ; ++q) loc[q] = 0.0;
+  const double inv_layer = 1.0 / (double)g.layer;
+  for (int z = threadIdx.x; z < nz; z += blockDim.x) {
+    double s[NQ];
+    for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+    for (int b = 0; b < nbx; ++b)
+      for (int q = 0; q < NQ; ++q) {
+        double v = partial[((int64_t)z * nbx + b) * NQ + q];
+        s[q] = (q == 6 || q == 7) ? fmax(s[q], v) : s[q] + v;
+      }
+    for (int q = 0; q < 4; ++q) out[q * nz + z] = s[q] * inv_layer;
+    for (int q = 0; q < NQ; ++q) loc[q] = (q == 6 || q == 7) ? fmax(loc[q], s[q]) : loc[q] + s[q];
+  }
+  __shared__ double red[256][NQ];
+  for (int q = 0; q < NQ; ++q) red[threadIdx.x][q] = loc[q];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < NQ; ++q)
+        red[threadIdx.x][q] = (q == 6 || q == 7) ? fmax(red[threadIdx.x][q], red[threadIdx.x + w][q])
+                                                 : red[threadIdx.x][q] + red[threadIdx.x + w][q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = out + 4 * nz;
+    o[OBS_ENERGY] = c.a[0] * c.a[1] * c.a[2] * red[0][0];
+    o[OBS_GAUSS_L2] = sqrt(red[0][4]);
+    o[OBS_RHO_L2] = sqrt(red[0][5]);
+    o[OBS_GAUSS_MAX] = red[0][6];
+    o[OBS_UNITARITY] = red[0][7];
+    o[OBS_NONFINITE] = red[0][8];
+    o[OBS_GAUSS_REL] = red[0][5] > 0 ? sqrt(red[0][4] / red[0][5]) : sqrt(red[0][4]);
+    o[7] = 0.0;
+  }
+}
+
+template <typename G, typename T>
+void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
+                    const StepConst& c, double* partial, double* out, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int nbx = obs_blocks_per_layer(g);
+  hipLaunchKernelGGL((k_observe<Gd, T>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+  hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
+}
+
+// ---- current of the next step (tests) --------------------------------------
+template <typename G, typename T>
+__global__ void k_current(const T* __restrict__ U, const T* __restrict__ rhoA, const T* __restrict__ rhoB,
+                          Geom g, StepConst c, T* __restrict__ j) {
+  using L = typename G::Link;
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int64_t V = g.V;
+  const int x = (int)(s % g.nt), y = (int)((s / g.nt) % g.nt), z = (int)(s / g.layer);
+  A jz = G::alg_zero();
+  if (c.hop) {
+    L Uz;
+    load_link(Uz, U, 2, s, V);
+    A rb, ra;
+    load_alg(rb, rhoB, site_index(g, x, y, slotB(z, c.offB, g.nz)), V);
+    load_alg(ra, rhoA, site_index(g, x, y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), V);
+    A ran = G::transport_inv(Uz, ra);
+    const typename G::Real k = (typename G::Real)(c.a[2] / c.dt);
+    for (int q = 0; q < NG; ++q) jz.c[q] = k * (ran.c[q] - rb.c[q]);
+  }
+  A zero = G::alg_zero();
+  store_alg(zero, j, s, V);
+  store_alg(zero, j + (int64_t)NG * V, s, V);
+  store_alg(jz, j + (int64_t)2 * NG * V, s, V);
+}
+
+template <typename G, typename T>
+void launch_current(const T* U, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c, T* j,
+                    hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_current<G, T>), dim3((unsigned)((g.V + bs - 1) / bs)), dim3(bs), 0, st, U, rhoA, rhoB, g, c, j);
+}
+
+// ---- FP64 reunitarisation ----------------------------------------------------
+template <typename Gd, typename T>
+__global__ void k_reunit(T* __restrict__ U, Geom g) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  for (int i = 0; i < 3; ++i) {
+    typename Gd::Link l;
+    load_link(l, U, i, s, g.V);
+    store_link(Gd::reunit(l), U, i, s, g.V);
+  }
+}
+
+template <typename G, typename T>
+void launch_reunit(T* U, const Geom& g, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int bs = 256;
+  hipLaunchKernelGGL((k_reunit<Gd, T>), dim3((unsigned)((g.V + bs - 1) / bs)), dim3(bs), 0, st, U, g);
+}
+
+#define GL_INST(G, T)                                                                                       \
+  template void launch_observe<G, T>(const T*, const T*, const T*, const T*, const Geom&, const StepConst&, \
+                                     double*, double*, hipStream_t);                                        \
+  template void launch_current<G, T>(const T*, const T*, const T*, const Geom&, const StepConst&, T*,      \
+                                     hipStream_t);                                                          \
+  template void launch_reunit<G, T>(T*, const Geom&, hipStream_t);
+GL_INST(Su2<double>, double)
+GL_INST(Su3<double>, double)
+GL_INST(Su2<float>, float)
+GL_INST(Su3<float>, float)
+
+}  // namespace gl

@@ -1,0 +1,115 @@
+"""Python front end of the HIP library: torch owns the device memory and the stream,
+every computation runs in libglasma.so.  Names follow the C-ABI (include/glasma.h)."""
+import ctypes as C
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import lib, check, dptr
+
+
+class Lattice:
+    """One event: SU(nc) links, E field and the two nuclei's CPIC charges on an
+    nz x nt x nt lattice held in caller-owned (torch) device buffers."""
+
+    def __init__(self, nc, nz, nt, a_T=4.0, a_L=1.0, dt=0.5, fp=64, scheme=0,
+                 reunit_every=0, max_iter=50, tol=0.0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU; no device is visible")
+        self.params = _lib.Params(nc, nz, nt, a_T, a_L, dt, fp, scheme, reunit_every, max_iter, tol)
+        sizes = (C.c_size_t * 6)()
+        check(lib.glasma_layout(C.byref(self.params), sizes))
+        self.sizes = list(sizes)
+        self.device = torch.device(device)
+        self._bufs = [torch.empty(max(int(s), 1), dtype=torch.uint8, device=self.device) for s in self.sizes]
+        b = _lib.Buffers(*[t.data_ptr() for t in self._bufs])
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        check(lib.glasma_create(C.byref(self.params), C.byref(b), C.c_void_p(self.stream.cuda_stream),
+                                C.byref(self.ctx)))
+        self.nc, self.nz, self.nt, self.fp = nc, nz, nt, fp
+        self.ng = nc * nc - 1
+        self.r = 4 if nc == 2 else 18
+        self.V = nz * nt * nt
+        self.real = torch.float64 if fp == 64 else torch.float32
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            lib.glasma_destroy(ctx)
+            self.ctx = None
+
+    def _chk(self, rc):
+        return check(rc, self.ctx)
+
+    # -- state ------------------------------------------------------------------
+    def init_state(self, U, E, rhoA, rhoB, step0=0):
+        """Host float64 arrays in the C-ABI layout: U (3, r_U, V), E (3, n_g, V), rho (n_g, V)."""
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (U, E, rhoA, rhoB)]
+        self._chk(lib.glasma_init_state(self.ctx, *[dptr(a) for a in arrs], int(step0)))
+
+    def init_mv(self, rhoT_A, rhoT_B, m_ir=0.2, uv_cut=0.0, sigma=4.0, zA=None, zB=None):
+        zA = 0.75 * self.nz * self.params.a_L if zA is None else zA
+        zB = 0.25 * self.nz * self.params.a_L if zB is None else zB
+        mv = _lib.MV(m_ir, uv_cut, sigma, zA, zB)
+        a = np.ascontiguousarray(rhoT_A, dtype=np.float64)
+        b = np.ascontiguousarray(rhoT_B, dtype=np.float64)
+        self._chk(lib.glasma_init_mv(self.ctx, C.byref(mv), dptr(a), dptr(b)))
+
+    def step(self, n=1):
+        self._chk(lib.glasma_step(self.ctx, int(n)))
+
+    def reunitarize(self):
+        self._chk(lib.glasma_reunitarize(self.ctx))
+
+    @property
+    def step_count(self):
+        s = C.c_int64()
+        self._chk(lib.glasma_get_step(self.ctx, C.byref(s)))
+        return s.value
+
+    def get_state(self):
+        U = np.empty((3, self.r, self.V))
+        E = np.empty((3, self.ng, self.V))
+        rA = np.empty((self.ng, self.V))
+        rB = np.empty((self.ng, self.V))
+        s = C.c_int64()
+        self._chk(lib.glasma_get_state(self.ctx, dptr(U), dptr(E), dptr(rA), dptr(rB), C.byref(s)))
+        return {"U": U, "E": E, "rhoA": rA, "rhoB": rB, "step": s.value}
+
+    # -- derived quantities -----------------------------------------------------
+    def deposit_current(self):
+        j = torch.empty(3 * self.ng * self.V, dtype=self.real, device=self.device)
+        self._chk(lib.glasma_deposit_current(self.ctx, C.c_void_p(j.data_ptr())))
+        return j
+
+    def obs_buffer(self):
+        return torch.empty(4 * self.nz + _lib.OBS_NSCALARS, dtype=torch.float64, device=self.device)
+
+    def observe(self, out):
+        """Asynchronous: write slices + scalars into the float64 device tensor `out`."""
+        self._chk(lib.glasma_observe(self.ctx, C.c_void_p(out.data_ptr())))
+
+    def observables(self):
+        t = np.empty((4, self.nz))
+        vals = [C.c_double() for _ in range(4)]
+        self._chk(lib.glasma_observables(self.ctx, dptr(t), *[C.byref(v) for v in vals]))
+        return {"tmunu_z": t, "gauss_rel": vals[0].value, "gauss_max": vals[1].value,
+                "energy": vals[2].value, "unitarity": vals[3].value}
+
+    @staticmethod
+    def unpack_obs(buf, nz):
+        h = buf.detach().cpu().numpy()
+        s = h[4 * nz:]
+        out = {k: float(s[v]) for k, v in _lib.OBS.items()}
+        out["tmunu_z"] = h[:4 * nz].reshape(4, nz)
+        return out
+
+
+def host_group_op(nc, fp, op, inp, n_out_per_item):
+    """Evaluate the device group algebra on the host (see glasma_host_group_op)."""
+    inp = np.ascontiguousarray(inp, dtype=np.float64)
+    n = inp.shape[0]
+    out = np.empty((n, n_out_per_item))
+    check(lib.glasma_host_group_op(nc, fp, op, n, dptr(inp), dptr(out)))
+    return out

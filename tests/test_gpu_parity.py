@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library (through the C-ABI) against the FP64 oracle on the same
+seeded inputs.  Per field component the bar is |d| <= 1e-10 max(|ref|, RMS of the
+field) over the first 20 steps; gauge-invariant observables 1e-8 relative over the
+full run (the dynamics is chaotic, so round-off differences grow)."""
+import sys
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice, init_mv, observables
+from _gpu import (gpu, lattice_or_skip, to_comp, from_comp, field_err, state_errs, mv_setup,
+                  new_lattice)
+
+pytestmark = gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _obs_close(go, oo, tol):
+    sl_ref = oo["tmunu_z"]
+    scale = np.abs(sl_ref).max(axis=1, keepdims=True)
+    err_sl = np.max(np.abs(go["tmunu_z"] - sl_ref) / scale)
+    err_H = abs(go["energy"] - oo["energy"]) / abs(oo["energy"])
+    assert err_sl < tol and err_H < tol, (err_sl, err_H)
+    return err_sl, err_H
+
+
+def test_leapfrog_su2_fp64_small_workload():
+    """SU(2) FP64, 64 x 8 x 8, MV nuclei, 100 steps (per-component parity over 20)."""
+    pkg = lattice_or_skip()
+    w = synth.SMALL_SU2
+    say("case: su2 fp64 64x8x8 leapfrog, seed", w.seed)
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    lat = new_lattice(pkg, w)
+    lat.init_state(*to_comp(st), step0=0)
+    worst = 0.0
+    for s in range(20):
+        st = lattice.leapfrog_step(st)
+        lat.step(1)
+        errs = state_errs(lat.get_state(), st)
+        worst = max(worst, max(errs.values()))
+        assert max(errs.values()) < 1e-10, (s, errs)
+    say("per-component worst over 20 steps", worst)
+    for s in range(20, w.steps):
+        if s % 10 == 0:
+            _obs_close(lat.observables(), observables.observables(st), 1e-8)
+        st = lattice.leapfrog_step(st)
+        lat.step(1)
+    go = lat.observables()
+    err = _obs_close(go, observables.observables(st), 1e-8)
+    say("observables at step 100", err)
+    assert go["gauss_rel"] < 1e-12
+
+
+@pytest.mark.parametrize("nc", [2, 3])
+def test_init_mv_matches_oracle(nc):
+    pkg = lattice_or_skip()
+    w = synth.SMALL_SU2 if nc == 2 else synth.Workload("su3-40x6x6", nc=3, nz=40, nt=6, mu=0.5,
+                                                        sigma=3.0, seed=77)
+    say("case: init_mv nc", nc, "dims", w.nz, w.nt)
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    lat = new_lattice(pkg, w)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    errs = state_errs(lat.get_state(), st)
+    say("init errs", errs)
+    assert max(errs.values()) < 1e-10, errs
+    o = lat.observables()
+    assert o["gauss_rel"] < 1e-13 and o["unitarity"] < 1e-13
+
+
+def test_leapfrog_su3_fp64_ragged_tiles():
+    """SU(3) FP64 on 24 x 10 x 10 (2400 sites: 9 full blocks of 256 + a ragged tail)."""
+    pkg = lattice_or_skip()
+    w = synth.Workload("su3-24x10x10", nc=3, nz=24, nt=10, mu=0.5, sigma=2.0, seed=91)
+    say("case: su3 fp64 24x10x10")
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    lat = new_lattice(pkg, w)
+    lat.init_state(*to_comp(st), step0=0)
+    for s in range(12):
+        st = lattice.leapfrog_step(st)
+        lat.step(1)
+        errs = state_errs(lat.get_state(), st)
+        assert max(errs.values()) < 1e-10, (s, errs)
+    _obs_close(lat.observables(), observables.observables(st), 1e-10)
+
+
+@pytest.mark.parametrize("dt,step0", [(0.5, 1), (1.0, 0), (0.25, 3)])
+def test_hop_phase_and_current(dt, step0):
+    """Hop schedule phase set by step0, and the deposited current against the oracle."""
+    pkg = lattice_or_skip()
+    w = synth.Workload("su2-16x4x4", nc=2, nz=16, nt=4, dt=dt, mu=1.0, sigma=1.5, seed=5)
+    say("case: hop phase dt", dt, "step0", step0)
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, 2, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    st.step = step0
+    lat = new_lattice(pkg, w)
+    lat.init_state(*to_comp(st), step0=step0)
+    for _ in range(6):
+        j = lat.deposit_current().cpu().numpy().reshape(3, 3, -1)
+        if lattice.is_hop_step(st.step, p):
+            _, _, jref = lattice.cpic_hop(st.U, st.rhoA, st.rhoB, p)
+        else:
+            jref = np.zeros_like(st.E)
+        from oracle import components
+        assert field_err(j, components.alg_to_comp(jref)) < 1e-12
+        st = lattice.leapfrog_step(st)
+        lat.step(1)
+        errs = state_errs(lat.get_state(), st)
+        assert max(errs.values()) < 1e-11, errs
+
+
+def test_observables_and_gauss_against_oracle_on_a_generic_state():
+    pkg = lattice_or_skip()
+    nc, dims = 3, (6, 5, 5)
+    p = lattice.Params(nc=nc, a_T=2.0, a_L=1.0, dt=0.5)
+    Ua = synth.normal(101, (3,) + dims + (8,), 0.9)
+    Ea = synth.normal(102, (3,) + dims + (8,), 0.4)
+    st = init_mv.state_from_algebra(Ua, Ea, p)
+    # a deliberate Gauss violation so the residual is non-trivial
+    st.rhoA = st.rhoA * 1.001
+    lat = pkg.Lattice(nc=nc, nz=dims[0], nt=dims[1], a_T=2.0, a_L=1.0, dt=0.5, fp=64)
+    lat.init_state(*to_comp(st), step0=1)
+    st.step = 1
+    go = lat.observables()
+    oo = observables.observables(st)
+    _obs_close(go, oo, 1e-12)
+    assert abs(go["gauss_rel"] - oo["gauss_rel"]) < 1e-10 * oo["gauss_rel"]
+    assert abs(go["gauss_max"] - oo["gauss_max"]) < 1e-10 * oo["gauss_max"]
+    assert go["unitarity"] < 1e-13
+
+
+def test_bitwise_reproducible_rerun():
+    pkg = lattice_or_skip()
+    w = synth.Workload("su3-32x8x8", nc=3, nz=32, nt=8, mu=0.5, sigma=2.0, seed=120)
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    out = []
+    for _ in range(2):
+        lat = new_lattice(pkg, w)
+        lat.init_mv(rA, rB, m_ir=w.m_ir, sigma=w.sigma)
+        lat.step(17)
+        out.append((lat.get_state(), lat.observables()))
+    for k in ("U", "E", "rhoA", "rhoB"):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert np.array_equal(out[0][1]["tmunu_z"], out[1][1]["tmunu_z"])
+
+
+def test_checkpoint_resume_bitwise():
+    """Run 2n steps == run n, download, upload into a new context, run n (bitwise)."""
+    pkg = lattice_or_skip()
+    w = synth.Workload("su2-32x6x6", nc=2, nz=32, nt=6, mu=1.0, sigma=2.0, seed=130)
+    rA, rB = synth.mv_charges(w.seed, 2, w.nt, w.mu, w.a_T)
+    a = new_lattice(pkg, w)
+    a.init_mv(rA, rB, sigma=w.sigma)
+    a.step(9)
+    mid = a.get_state()
+    a.step(9)
+    full = a.get_state()
+    b = new_lattice(pkg, w)
+    b.init_state(mid["U"], mid["E"], mid["rhoA"], mid["rhoB"], step0=mid["step"])
+    b.step(9)
+    res = b.get_state()
+    for k in ("U", "E", "rhoA", "rhoB"):
+        assert np.array_equal(res[k], full[k]), k
+    assert res["step"] == full["step"] == 18
+
+
+def test_fp32_precision_form_against_fp64_oracle():
+    """FP32 links and fields with FP64 reunitarisation every 8 steps: gauge-invariant
+    observables within 1e-4 relative of the FP64 oracle."""
+    pkg = lattice_or_skip()
+    w = synth.Workload("su3-48x8x8", nc=3, nz=48, nt=8, mu=0.5, sigma=3.0, seed=140)
+    say("case: fp32 su3 48x8x8")
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    lat = new_lattice(pkg, w, fp=32, reunit_every=8)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    worst = 0.0
+    for blk in range(6):
+        st = lattice.evolve(st, 8)
+        lat.step(8)
+        go, oo = lat.observables(), observables.observables(st)
+        e_sl, e_H = _obs_close(go, oo, 1e-4)
+        worst = max(worst, e_sl, e_H)
+        assert go["unitarity"] < 1e-5
+    say("fp32 worst observable error over 48 steps", worst)
+
+
+def test_full_size_plain_su3_sampled():
+    """SU(3) FP64 at the full 512 x 64 x 64 size in the benchmark's launch configuration:
+    MV initial state on the GPU, 4 steps; properties that hold at any size (Gauss
+    law, unitarity), and the E update at sampled sites recomputed by the oracle."""
+    pkg = lattice_or_skip()
+    w = synth.PLAIN_SU3
+    say("case: full-size su3 512x64x64")
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    lat = new_lattice(pkg, w)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma)
+    lat.step(3)
+    before = from_comp(lat.get_state(), 3, (w.nz, w.nt, w.nt), lattice.Params(3, w.a_T, w.a_L, w.dt))
+    o = lat.observables()
+    assert o["gauss_rel"] < 1e-12 and o["unitarity"] < 1e-13
+    lat.step(1)
+    after = lat.get_state()
+    g = synth.rng(7)
+    sites = [(int(g.integers(w.nz)), int(g.integers(w.nt)), int(g.integers(w.nt))) for _ in range(24)]
+    sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 5, w.nt - 1)]
+    p = before.params
+    hop = lattice.is_hop_step(before.step, p)
+    assert not hop            # step 3 is not a hop step at dt = a_L/2
+    from oracle import su
+    for (z, y, x) in sites:
+        F = lattice.force_at_site(before.U, p.a, (z, y, x))
+        E_ref = before.E[:, z, y, x] + p.dt * F
+        s = (z * w.nt + y) * w.nt + x
+        E_got = su.from_components(after["E"][:, :, s], 3)
+        np.testing.assert_allclose(E_got, E_ref, atol=1e-12 * max(1.0, np.abs(E_ref).max()))
