@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libglasma.so")
+# GLASMA_LIB selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("GLASMA_LIB") or os.path.join(HERE, "libglasma.so")
 
 GLASMA_OK = 0
 ERRORS = {-1: "GLASMA_E_ARG", -2: "GLASMA_E_HIP", -3: "GLASMA_E_NONFINITE",

@@ -79,6 +79,7 @@ static Geom geom_of(const glasma_params* p) {
   g.nz = p->nz;
   g.layer = (int64_t)p->nt * p->nt;
   g.V = g.layer * p->nz;
+  g.Vp = padded_sites(g.V);
   return g;
 }
 
@@ -124,10 +125,10 @@ int glasma_layout(const glasma_params* p, size_t* bytes) {
   Geom g = geom_of(p);
   const size_t e = elem(p);
   const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
-  bytes[0] = 3 * (size_t)r * g.V * e;
+  bytes[0] = 3 * (size_t)r * g.Vp * e;
   bytes[1] = bytes[0];
-  bytes[2] = 3 * (size_t)ng * g.V * e;
-  bytes[3] = (size_t)ng * g.V * e;
+  bytes[2] = 3 * (size_t)ng * g.Vp * e;
+  bytes[3] = (size_t)ng * g.Vp * e;
   bytes[4] = bytes[3];
   bytes[5] = work_doubles(p) * sizeof(double);
   return GLASMA_OK;
@@ -169,11 +170,18 @@ int glasma_get_step(const glasma_ctx* ctx, int64_t* step) {
   return GLASMA_OK;
 }
 
+// Host SoA [dir][comp][V] (double) <-> device tiled records (type T), see lattice.h.
 template <typename T>
-static int upload(glasma_ctx* c, void* dst, const double* src, size_t n) {
-  std::vector<T> tmp(n);
-  for (size_t k = 0; k < n; ++k) tmp[k] = (T)src[k];
-  HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+static int upload(glasma_ctx* c, void* dst, const double* src, int ndir, int width) {
+  const int64_t V = c->g.V, Vp = c->g.Vp;
+  std::vector<T> tmp((size_t)ndir * width * Vp, T(0));
+  for (int d = 0; d < ndir; ++d)
+    for (int k = 0; k < width; ++k) {
+      const double* sp = src + ((int64_t)d * width + k) * V;
+      T* dp = tmp.data() + (int64_t)d * width * Vp;
+      for (int64_t s = 0; s < V; ++s) dp[rec_elem<T>(s, k, width)] = (T)sp[s];
+    }
+  HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return GLASMA_OK;
 }
@@ -185,10 +193,10 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
   const size_t V = c->g.V;
   int rc = dispatch(c, [&]<typename G, typename T>() -> int {
     int r;
-    if ((r = upload<T>(c, c->b.U, U, 3 * (size_t)c->r * V))) return r;
-    if ((r = upload<T>(c, c->b.E, E, 3 * (size_t)c->ng * V))) return r;
-    if ((r = upload<T>(c, c->b.rhoA, rhoA, (size_t)c->ng * V))) return r;
-    if ((r = upload<T>(c, c->b.rhoB, rhoB, (size_t)c->ng * V))) return r;
+    if ((r = upload<T>(c, c->b.U, U, 3, c->r))) return r;
+    if ((r = upload<T>(c, c->b.E, E, 3, c->ng))) return r;
+    if ((r = upload<T>(c, c->b.rhoA, rhoA, 1, c->ng))) return r;
+    if ((r = upload<T>(c, c->b.rhoB, rhoB, 1, c->ng))) return r;
     return GLASMA_OK;
   });
   if (rc) return rc;
@@ -307,37 +315,37 @@ int glasma_observables(glasma_ctx* c, double* tmunu_z, double* gauss_rel, double
   return GLASMA_OK;
 }
 
-template <typename T>
-static int download(glasma_ctx* c, double* dst, const void* src, size_t n) {
-  std::vector<T> tmp(n);
-  HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+// zsrc(z) gives the stored layer that holds physical layer z (co-moving charges).
+template <typename T, typename F>
+static int download(glasma_ctx* c, double* dst, const void* src, int ndir, int width, F zsrc) {
+  const int64_t V = c->g.V, Vp = c->g.Vp, layer = c->g.layer;
+  std::vector<T> tmp((size_t)ndir * width * Vp);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (size_t k = 0; k < n; ++k) dst[k] = (double)tmp[k];
+  for (int d = 0; d < ndir; ++d)
+    for (int k = 0; k < width; ++k) {
+      double* dp = dst + ((int64_t)d * width + k) * V;
+      const T* sp = tmp.data() + (int64_t)d * width * Vp;
+      for (int z = 0; z < c->g.nz; ++z) {
+        const int64_t zs = zsrc(z);
+        for (int64_t t = 0; t < layer; ++t) dp[z * layer + t] = (double)sp[rec_elem<T>(zs * layer + t, k, width)];
+      }
+    }
   return GLASMA_OK;
 }
 
 int glasma_get_state(glasma_ctx* c, double* U, double* E, double* rhoA, double* rhoB, int64_t* step) {
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
-  const size_t V = c->g.V;
-  const int64_t layer = c->g.layer;
   const int nz = c->g.nz;
   int rc = dispatch(c, [&]<typename G, typename T>() -> int {
     int r;
-    if (U && (r = download<T>(c, U, cur_U<T>(c), 3 * (size_t)c->r * V))) return r;
-    if (E && (r = download<T>(c, E, c->b.E, 3 * (size_t)c->ng * V))) return r;
-    std::vector<double> tmp((size_t)c->ng * V);
-    for (int pop = 0; pop < 2; ++pop) {
-      double* dst = pop == 0 ? rhoA : rhoB;
-      if (!dst) continue;
-      if ((r = download<T>(c, tmp.data(), pop == 0 ? c->b.rhoA : c->b.rhoB, tmp.size()))) return r;
-      for (int a = 0; a < c->ng; ++a)
-        for (int z = 0; z < nz; ++z) {
-          int slot = pop == 0 ? slotA(z, c->offA, nz) : slotB(z, c->offB, nz);
-          std::memcpy(dst + (size_t)a * V + (size_t)z * layer, tmp.data() + (size_t)a * V + (size_t)slot * layer,
-                      layer * sizeof(double));
-        }
-    }
+    auto same = [](int z) { return z; };
+    const int oA = c->offA, oB = c->offB;
+    if (U && (r = download<T>(c, U, cur_U<T>(c), 3, c->r, same))) return r;
+    if (E && (r = download<T>(c, E, c->b.E, 3, c->ng, same))) return r;
+    if (rhoA && (r = download<T>(c, rhoA, c->b.rhoA, 1, c->ng, [&](int z) { return slotA(z, oA, nz); }))) return r;
+    if (rhoB && (r = download<T>(c, rhoB, c->b.rhoB, 1, c->ng, [&](int z) { return slotB(z, oB, nz); }))) return r;
     return GLASMA_OK;
   });
   if (rc) return rc;

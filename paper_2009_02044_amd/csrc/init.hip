@@ -121,8 +121,8 @@ __global__ void k_ic_links(const double* __restrict__ phi, T* __restrict__ U, T*
     typename Gd::Alg e = Gd::logi(Gd::mul_dag(U0, U1));
     const double k = 1.0 / (c.a[i] * c.dt);
     for (int q = 0; q < NG; ++q) e.c[q] *= k;
-    store_link(U0, U, i, s, g.V);
-    store_alg(e, E + (int64_t)i * NG * g.V, s, g.V);
+    store_link(U0, U, i, (uint32_t)s, g.Vp);
+    store_alg(e, E, i, (uint32_t)s, g.Vp);
   }
 }
 
@@ -132,24 +132,24 @@ __global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, T* 
   constexpr int NG = Gd::NG;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
   Site x;
   x.x = (int)(s % g.nt); x.y = (int)((s / g.nt) % g.nt); x.z = (int)(s / g.layer);
   typename Gd::Alg r = Gd::alg_zero();
   for (int i = 0; i < 3; ++i) {
     const int64_t sm = idx(g, shifted(g, x, i, -1));
     typename Gd::Link Um;
-    load_link(Um, U, i, sm, V);
+    load_link(Um, U, i, sm, Vp);
     typename Gd::Alg eh, em;
-    load_alg(eh, E + (int64_t)i * NG * V, s, V);
-    load_alg(em, E + (int64_t)i * NG * V, sm, V);
+    load_alg(eh, E, i, s, Vp);
+    load_alg(em, E, i, sm, Vp);
     typename Gd::Alg tr = Gd::transport(Um, em);
     for (int q = 0; q < NG; ++q) r.c[q] += (eh.c[q] - tr.c[q]) / c.a[i];
   }
   typename Gd::Alg zero = Gd::alg_zero();
   const bool isB = x.z < g.nz / 2;
-  store_alg(isB ? r : zero, rhoB, s, V);
-  store_alg(isB ? zero : r, rhoA, s, V);
+  store_alg(isB ? r : zero, rhoB, 0, s, Vp);
+  store_alg(isB ? zero : r, rhoA, 0, s, Vp);
 }
 
 template <typename G, typename T>

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
   using L = typename G::Link;   // double precision group
   using A = typename G::Alg;
   constexpr int NG = G::NG;
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
   const int z = blockIdx.y;
   const int nbx = gridDim.x;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
@@ -71,15 +71,15 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     for (int i = 0; i < 3; ++i) {
       L S = staple_sum<G, T>(U, g, x, i, inv_a2);
       L Ui;
-      load_link(Ui, U, i, s, V);
+      load_link(Ui, U, i, s, Vp);
       A f = G::proj(G::mul(Ui, S));
       A eo, en;
-      load_alg(eo, E + (int64_t)i * NG * V, s, V);
+      load_alg(eo, E, i, s, Vp);
       for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k] - c.dt / c.a[i] * f.c[k];
       if (c.hop && i == 2) {
         A rb, ra;
-        load_alg(rb, rhoB, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), V);
-        load_alg(ra, rhoA, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), V);
+        load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
+        load_alg(ra, rhoA, 0, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), Vp);
         A ran = G::transport_inv(Ui, ra);
         for (int k = 0; k < NG; ++k) en.c[k] += c.a[2] * (ran.c[k] - rb.c[k]);
       }
@@ -109,17 +109,17 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     acc[3] += sl;
     // Gauss residual at (U(t), E(t - dt/2), rho(t - dt/2))
     A G_, r, rb;
-    load_alg(r, rhoA, site_index(g, x.x, x.y, slotA(z, c.offA, g.nz)), V);
-    load_alg(rb, rhoB, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), V);
+    load_alg(r, rhoA, 0, site_index(g, x.x, x.y, slotA(z, c.offA, g.nz)), Vp);
+    load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
     for (int k = 0; k < NG; ++k) { r.c[k] += rb.c[k]; G_.c[k] = -r.c[k]; }
     for (int i = 0; i < 3; ++i) {
       Site xm = shifted(g, x, i, -1);
       const int64_t sm = idx(g, xm);
       L Um;
-      load_link(Um, U, i, sm, V);
+      load_link(Um, U, i, sm, Vp);
       A eh, em;
-      load_alg(eh, E + (int64_t)i * NG * V, s, V);
-      load_alg(em, E + (int64_t)i * NG * V, sm, V);
+      load_alg(eh, E, i, s, Vp);
+      load_alg(em, E, i, sm, Vp);
       A tr = G::transport(Um, em);
       for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tr.c[k]) / c.a[i];
     }
@@ -206,23 +206,23 @@ __global__ void k_current(const T* __restrict__ U, const T* __restrict__ rhoA, c
   constexpr int NG = G::NG;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
   const int x = (int)(s % g.nt), y = (int)((s / g.nt) % g.nt), z = (int)(s / g.layer);
   A jz = G::alg_zero();
   if (c.hop) {
     L Uz;
-    load_link(Uz, U, 2, s, V);
+    load_link(Uz, U, 2, s, Vp);
     A rb, ra;
-    load_alg(rb, rhoB, site_index(g, x, y, slotB(z, c.offB, g.nz)), V);
-    load_alg(ra, rhoA, site_index(g, x, y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), V);
+    load_alg(rb, rhoB, 0, site_index(g, x, y, slotB(z, c.offB, g.nz)), Vp);
+    load_alg(ra, rhoA, 0, site_index(g, x, y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), Vp);
     A ran = G::transport_inv(Uz, ra);
     const typename G::Real k = (typename G::Real)(c.a[2] / c.dt);
     for (int q = 0; q < NG; ++q) jz.c[q] = k * (ran.c[q] - rb.c[q]);
   }
   A zero = G::alg_zero();
-  store_alg(zero, j, s, V);
-  store_alg(zero, j + (int64_t)NG * V, s, V);
-  store_alg(jz, j + (int64_t)2 * NG * V, s, V);
+  store_alg(zero, j, 0, s, Vp);
+  store_alg(zero, j, 1, s, Vp);
+  store_alg(jz, j, 2, s, Vp);
 }
 
 template <typename G, typename T>
@@ -237,10 +237,11 @@ template <typename Gd, typename T>
 __global__ void k_reunit(T* __restrict__ U, Geom g) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
+  const int64_t Vp = g.Vp;
   for (int i = 0; i < 3; ++i) {
     typename Gd::Link l;
-    load_link(l, U, i, s, g.V);
-    store_link(Gd::reunit(l), U, i, s, g.V);
+    load_link(l, U, i, s, Vp);
+    store_link(Gd::reunit(l), U, i, s, Vp);
   }
 }
 

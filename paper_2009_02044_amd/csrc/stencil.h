@@ -13,7 +13,7 @@ __device__ __forceinline__ typename G::Link staple_sum(const T* __restrict__ U, 
   using L = typename G::Link;
   using R = typename G::Real;
   L S = G::zero();
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
   Site xpi = shifted(g, x, i, +1);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -23,13 +23,13 @@ __device__ __forceinline__ typename G::Link staple_sum(const T* __restrict__ U, 
     Site xmj = shifted(g, x, j, -1);
     Site xpimj = shifted(g, xpi, j, -1);
     L A, B, C;
-    load_link(A, U, j, idx(g, xpi), V);
-    load_link(B, U, i, idx(g, xpj), V);
-    load_link(C, U, j, idx(g, x), V);
+    load_link(A, U, j, idx(g, xpi), Vp);
+    load_link(B, U, i, idx(g, xpj), Vp);
+    load_link(C, U, j, idx(g, x), Vp);
     G::add_to(S, G::mul_dag(G::mul_dag(A, B), C), w);
-    load_link(A, U, j, idx(g, xpimj), V);
-    load_link(B, U, i, idx(g, xmj), V);
-    load_link(C, U, j, idx(g, xmj), V);
+    load_link(A, U, j, idx(g, xpimj), Vp);
+    load_link(B, U, i, idx(g, xmj), Vp);
+    load_link(C, U, j, idx(g, xmj), Vp);
     G::add_to(S, G::dag_mul(G::mul(B, A), C), w);
   }
   return S;
@@ -41,12 +41,12 @@ template <typename G, typename T>
 __device__ __forceinline__ typename G::Link plaquette(const T* __restrict__ U, const Geom& g, Site x,
                                                       int i, int j) {
   using L = typename G::Link;
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
   L Ui, A, B, C;
-  load_link(Ui, U, i, idx(g, x), V);
-  load_link(A, U, j, idx(g, shifted(g, x, i, +1)), V);
-  load_link(B, U, i, idx(g, shifted(g, x, j, +1)), V);
-  load_link(C, U, j, idx(g, x), V);
+  load_link(Ui, U, i, idx(g, x), Vp);
+  load_link(A, U, j, idx(g, shifted(g, x, i, +1)), Vp);
+  load_link(B, U, i, idx(g, shifted(g, x, j, +1)), Vp);
+  load_link(C, U, j, idx(g, x), Vp);
   return G::mul_dag(G::mul_dag(G::mul(Ui, A), B), C);
 }
 

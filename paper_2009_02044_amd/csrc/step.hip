@@ -19,51 +19,81 @@
 
 namespace gl {
 
+// Update of link (x, i): staples, E, CPIC hop (z links on hop steps), exp, new link.
 template <typename G, typename T, bool HOP>
-__global__ void __launch_bounds__(256) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
-                                                  T* __restrict__ E, T* __restrict__ rhoA,
-                                                  T* __restrict__ rhoB, Geom g, StepConst c) {
+__device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restrict__ Unew, T* __restrict__ E,
+                                            T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
+                                            const StepConst& c, const double* inv_a2, Site x, uint32_t s, int i) {
   using L = typename G::Link;
   using A = typename G::Alg;
   constexpr int NG = G::NG;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
-  const int64_t V = g.V;
+  const int64_t Vp = g.Vp;
+  L S = staple_sum<G, T>(U, g, x, i, inv_a2);
+  L Ui;
+  load_link(Ui, U, i, s, Vp);
+  A f = G::proj(G::mul(Ui, S));
+  A e;
+  load_alg(e, E, i, s, Vp);
+  const T kf = (T)(-c.dt / c.a[i]);
+#pragma unroll
+  for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
+  if (HOP && i == 2) {
+    const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
+    const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
+    A rb, ra;
+    load_alg(rb, rhoB, 0, sB, Vp);
+    load_alg(ra, rhoA, 0, sA, Vp);
+    A rbn = G::transport(Ui, rb);
+    A ran = G::transport_inv(Ui, ra);
+    store_alg(rbn, rhoB, 0, sB, Vp);
+    store_alg(ran, rhoA, 0, sA, Vp);
+    // dt * j_z = a_L (rho_A' - rho_B)
+    const T al = (T)c.a[2];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
+  }
+  store_alg(e, E, i, s, Vp);
+  L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
+  store_link(Un, Unew, i, s, Vp);
+}
+
+#ifndef GL_LF_WAVES
+#define GL_LF_WAVES 1
+#endif
+#ifndef GL_LF_PER_DIR
+#define GL_LF_PER_DIR 0
+#endif
+
+// One thread per site, the three directions in turn.
+template <typename G, typename T, bool HOP>
+__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
+                                                               T* __restrict__ E, T* __restrict__ rhoA,
+                                                               T* __restrict__ rhoB, Geom g, StepConst c) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
   Site x;
-  x.x = (int)(s % g.nt);
-  x.y = (int)((s / g.nt) % g.nt);
-  x.z = (int)(s / g.layer);
+  x.x = (int)(s % (uint32_t)g.nt);
+  x.y = (int)((s / (uint32_t)g.nt) % (uint32_t)g.nt);
+  x.z = (int)(s / (uint32_t)g.layer);
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
 #pragma unroll 1
-  for (int i = 0; i < 3; ++i) {
-    L S = staple_sum<G, T>(U, g, x, i, inv_a2);
-    L Ui;
-    load_link(Ui, U, i, s, V);
-    A f = G::proj(G::mul(Ui, S));
-    A e;
-    load_alg(e, E + (int64_t)i * NG * V, s, V);
-    const T kf = (T)(-c.dt / c.a[i]);
-#pragma unroll
-    for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
-    if (HOP && i == 2) {
-      const int64_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
-      const int64_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
-      A rb, ra;
-      load_alg(rb, rhoB, sB, V);
-      load_alg(ra, rhoA, sA, V);
-      A rbn = G::transport(Ui, rb);
-      A ran = G::transport_inv(Ui, ra);
-      store_alg(rbn, rhoB, sB, V);
-      store_alg(ran, rhoA, sA, V);
-      // dt * j_z = a_L (rho_A' - rho_B)
-      const T al = (T)c.a[2];
-#pragma unroll
-      for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
-    }
-    store_alg(e, E + (int64_t)i * NG * V, s, V);
-    L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
-    store_link(Un, Unew, i, s, V);
-  }
+  for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
+}
+
+// One thread per link: direction i = blockIdx.y, uniform over the block.
+template <typename G, typename T, bool HOP>
+__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog_dir(const T* __restrict__ U, T* __restrict__ Unew,
+                                                                   T* __restrict__ E, T* __restrict__ rhoA,
+                                                                   T* __restrict__ rhoB, Geom g, StepConst c) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  Site x;
+  x.x = (int)(s % (uint32_t)g.nt);
+  x.y = (int)((s / (uint32_t)g.nt) % (uint32_t)g.nt);
+  x.z = (int)(s / (uint32_t)g.layer);
+  const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
+  const int i = blockIdx.y;
+  update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
 }
 
 template <typename G, typename T>
@@ -71,10 +101,17 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
                      hipStream_t st) {
   const int bs = 256;
   const int64_t nb = (g.V + bs - 1) / bs;
-  if (c.hop)
-    hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
-  else
-    hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+  if (GL_LF_PER_DIR) {
+    if (c.hop)
+      hipLaunchKernelGGL((k_leapfrog_dir<G, T, true>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+    else
+      hipLaunchKernelGGL((k_leapfrog_dir<G, T, false>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+  } else {
+    if (c.hop)
+      hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+    else
+      hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+  }
 }
 
 template void launch_leapfrog<Su2<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);

@@ -198,7 +198,7 @@ def test_fp32_precision_form_against_fp64_oracle():
 
 def test_full_size_plain_su3_sampled():
     """SU(3) FP64 at the full 512 x 64 x 64 size in the benchmark's launch configuration:
-    MV initial state on the GPU, 4 steps; properties that hold at any size (Gauss
+    MV initial state on the GPU, 5 steps; properties that hold at any size (Gauss
     law, unitarity), and the E update at sampled sites recomputed by the oracle."""
     pkg = lattice_or_skip()
     w = synth.PLAIN_SU3
@@ -206,7 +206,7 @@ def test_full_size_plain_su3_sampled():
     rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
     lat = new_lattice(pkg, w)
     lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma)
-    lat.step(3)
+    lat.step(4)
     before = from_comp(lat.get_state(), 3, (w.nz, w.nt, w.nt), lattice.Params(3, w.a_T, w.a_L, w.dt))
     o = lat.observables()
     assert o["gauss_rel"] < 1e-12 and o["unitarity"] < 1e-13
@@ -217,7 +217,7 @@ def test_full_size_plain_su3_sampled():
     sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 5, w.nt - 1)]
     p = before.params
     hop = lattice.is_hop_step(before.step, p)
-    assert not hop            # step 3 is not a hop step at dt = a_L/2
+    assert not hop            # hops happen on odd steps at dt = a_L/2
     from oracle import su
     for (z, y, x) in sites:
         F = lattice.force_at_site(before.U, p.a, (z, y, x))
