@@ -25,9 +25,12 @@
  *   links  U[i][c][s], i = 0:x 1:y 2:z; SU(2): c = 0..3, U = u0 + i (u1 s1 + u2 s2 + u3 s3);
  *          SU(3): c = 2 (3 r + k) + {0 Re, 1 Im} for matrix entry (r, k)
  *   E      E[i][a][s];  charges rho[a][s] at their physical lattice positions.
- * Device buffers use the same ordering in the context's precision (fp = 64: double,
- * fp = 32: float); the charge buffers are stored co-moving with their nucleus, so
- * read them through glasma_get_state.
+ * Device buffers hold the same fields in the context's precision (fp = 64: double,
+ * fp = 32: float) in a tiled layout: per direction, records of 64 consecutive sites
+ * in which the components are grouped in 16-byte chunks, one row of 64 chunks per
+ * group; the site count is padded to Vp = 64 ceil(V/64).  The charge
+ * buffers are stored co-moving with their nucleus.  Read and write device state only
+ * through glasma_init_state / glasma_get_state.
  *
  * Memory: the caller allocates every device buffer (sizes from glasma_layout) and
  * keeps it alive until glasma_destroy; the library never allocates or frees device
@@ -71,11 +74,11 @@ typedef struct {
 
 /* Device buffers (caller-owned; sizes in bytes from glasma_layout, same order). */
 typedef struct {
-  void* U;      /* links at the current time, 3 * r_U * V reals (r_U = 4 or 18) */
+  void* U;      /* links at the current time, 3 * r_U * Vp reals (r_U = 4 or 18) */
   void* U_alt;  /* second link buffer of the same size (the step writes into it) */
-  void* E;      /* electric field, 3 * n_g * V reals */
-  void* rhoA;   /* charges of nucleus A, n_g * V reals (co-moving storage) */
-  void* rhoB;   /* charges of nucleus B, n_g * V reals (co-moving storage) */
+  void* E;      /* electric field, 3 * n_g * Vp reals */
+  void* rhoA;   /* charges of nucleus A, n_g * Vp reals (co-moving storage) */
+  void* rhoB;   /* charges of nucleus B, n_g * Vp reals (co-moving storage) */
   void* work;   /* scratch: initial conditions, reductions, iterations */
 } glasma_buffers;
 
@@ -131,7 +134,8 @@ int glasma_init_mv(glasma_ctx* ctx, const glasma_mv* mv, const double* rhoT_A, c
  * reunit_every steps when set).  Asynchronous for the leapfrog. */
 int glasma_step(glasma_ctx* ctx, int32_t n);
 
-/* Current j (device, 3 * n_g * V reals of the context's precision, layout of E) that
+/* Current j (device, 3 * n_g * V reals of the context's precision, in the plain host
+ * layout j[i][a][s] -- not the tiled device layout of E) that
  * the next step deposits: j_z = (a_L/dt)(rho_A' - rho_B) on hop steps (rho_A' is
  * the transported A charge), zero otherwise (Sec. 3, eq. continuity).  Does not
  * change the state.  Asynchronous. */

@@ -57,6 +57,14 @@ template <typename T> struct Su2 {
   // (U - U^dag)/(2i) = q.s  ->  components 2 q_a
   static GL_HD Alg proj(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
   static GL_HD T retr(const Link& m) { return 2 * m.q[0]; }               // Re Tr
+  // proj(a b): only the vector part of the product
+  static GL_HD Alg proj_mul(const Link& a, const Link& b) {
+    Alg r;
+    r.c[0] = 2 * (a.q[0] * b.q[1] + b.q[0] * a.q[1] - (a.q[2] * b.q[3] - a.q[3] * b.q[2]));
+    r.c[1] = 2 * (a.q[0] * b.q[2] + b.q[0] * a.q[2] - (a.q[3] * b.q[1] - a.q[1] * b.q[3]));
+    r.c[2] = 2 * (a.q[0] * b.q[3] + b.q[0] * a.q[3] - (a.q[1] * b.q[2] - a.q[2] * b.q[1]));
+    return r;
+  }
   // exp(i s X), X = x.s/2: cos(|sx|/2) + i sin(|sx|/2) n.s
   static GL_HD Link expi(const Alg& x, T s) {
     T v0 = s * x.c[0], v1 = s * x.c[1], v2 = s * x.c[2];
@@ -201,6 +209,33 @@ template <typename T> struct Su3 {
     return r;
   }
   static GL_HD T retr(const Link& m) { return m.re[0][0] + m.re[1][1] + m.re[2][2]; }
+  // proj(a b) from the six off-diagonal entries and the imaginary diagonal of a b
+  static GL_HD Alg proj_mul(const Link& a, const Link& b) {
+    T mr[3][3], mi[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (i != j) sr += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
+          si += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+        }
+        mr[i][j] = sr; mi[i][j] = si;
+      }
+    const T is3 = T(0.57735026918962576451);
+    Alg r;
+    r.c[0] = mi[0][1] + mi[1][0];
+    r.c[1] = mr[0][1] - mr[1][0];
+    r.c[2] = mi[0][0] - mi[1][1];
+    r.c[3] = mi[0][2] + mi[2][0];
+    r.c[4] = mr[0][2] - mr[2][0];
+    r.c[5] = mi[1][2] + mi[2][1];
+    r.c[6] = mr[1][2] - mr[2][1];
+    r.c[7] = (mi[0][0] + mi[1][1] - T(2) * mi[2][2]) * is3;
+    return r;
+  }
   // hermitian matrix X = sum_a x^a lambda^a / 2, scaled by s
   static GL_HD Link herm(const Alg& x, T s) {
     const T is3 = T(0.57735026918962576451);
@@ -232,95 +267,91 @@ template <typename T> struct Su3 {
     return r;
   }
 
-  // exp(i Q), Q = s x^a t^a hermitian traceless, by the Cayley-Hamilton closed form of
-  // Morningstar & Peardon, Phys. Rev. D 69, 054501 (2004): exp(iQ) = f0 + f1 Q + f2 Q^2
-  // with c0 = det Q, c1 = Tr Q^2 / 2, eigenvalues 2u, -u +- w.  For tiny c1 the
-  // power series of exp is summed with Q^3 = c1 Q + c0 reducing every power.
+  // Q^2 for hermitian Q (the result is hermitian: upper triangle computed, lower mirrored)
+  static GL_HD Link herm_sq(const Link& Q) {
+    Link r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          sr += Q.re[i][k] * Q.re[k][j] - Q.im[i][k] * Q.im[k][j];
+          si += Q.re[i][k] * Q.im[k][j] + Q.im[i][k] * Q.re[k][j];
+        }
+        r.re[i][j] = sr; r.im[i][j] = (i == j) ? T(0) : si;
+        if (j != i) { r.re[j][i] = sr; r.im[j][i] = -si; }
+      }
+    return r;
+  }
+
+  // exp(i Q) for Q = s x^a t^a hermitian traceless.  By Cayley-Hamilton every power of
+  // Q is a combination of 1, Q, Q^2 (Q^3 = c1 Q + c0 with c0 = det Q = Tr Q^3 / 3,
+  // c1 = Tr Q^2 / 2), so exp(iQ) = h0 + h1 Q + h2 Q^2 with complex scalars h.  They
+  // are obtained by scaling and squaring in that coefficient space: the exponential
+  // series of Q / 2^k (spectral radius <= 1/2, sqrt(4 c1 / 3) bounds it) is summed to
+  // a remainder below the unit roundoff (14 terms in double, 8 in float), and each of
+  // the k squarings (h0 + h1 Q + h2 Q^2)^2 is reduced with the same identity.  Exact
+  // to rounding; no transcendental functions and no branches on the data apart from k.
   static GL_HD Link expi(const Alg& x, T s) {
     Link Q = herm(x, s);
-    Link Q2 = mul(Q, Q);
-    T c1 = T(0.5) * (Q2.re[0][0] + Q2.re[1][1] + Q2.re[2][2]);
-    // det Q = Tr(Q^3)/3 for traceless Q
+    Link Q2 = herm_sq(Q);
+    const T c1 = T(0.5) * (Q2.re[0][0] + Q2.re[1][1] + Q2.re[2][2]);
     T trq3 = T(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k) trq3 += Q.re[i][k] * Q2.re[k][i] - Q.im[i][k] * Q2.im[k][i];
-    T c0 = trq3 / T(3);
-    T f0r, f0i, f1r, f1i, f2r, f2i;
-    const T small = sizeof(T) == 8 ? T(1e-6) : T(1e-3);
-    if (c1 < small) {
-      // sum_n (i^n/n!) Q^n with Q^n = a_n + b_n Q + c_n Q^2
-      T a = 1, b = 0, c = 0;             // Q^0
-      f0r = 1; f0i = 0; f1r = 0; f1i = 0; f2r = 0; f2i = 0;
-      T fact = 1;
-      const int nterm = sizeof(T) == 8 ? 14 : 9;
-      for (int n = 1; n <= nterm; ++n) {
-        T an = c0 * c, bn = a + c1 * c, cn = b;
-        a = an; b = bn; c = cn;
-        fact *= T(n);
-        T w = T(1) / fact;
-        int ph = n & 3;               // i^n = 1, i, -1, -i
-        T wr = (ph == 0) ? w : (ph == 2 ? -w : T(0));
-        T wi = (ph == 1) ? w : (ph == 3 ? -w : T(0));
-        f0r += wr * a; f0i += wi * a;
-        f1r += wr * b; f1i += wi * b;
-        f2r += wr * c; f2i += wi * c;
-      }
-    } else {
-      bool neg = c0 < T(0);
-      T c0a = neg ? -c0 : c0;
-      T sq = sqrt(c1 / T(3));
-      T c0max = T(2) * sq * sq * sq;
-      T r = c0a / c0max;
-      r = r > T(1) ? T(1) : r;
-      T theta = acos(r);
-      T st, ct;
-      sincos_r<T>(theta / T(3), &st, &ct);
-      T u = sq * ct;
-      T w = sqrt(c1) * st;
-      T u2 = u * u, w2 = w * w;
-      T sw, cw;
-      sincos_r<T>(w, &sw, &cw);
-      T xi0 = (fabs(w) < T(0.05)) ? T(1) - w2 / T(6) * (T(1) - w2 / T(20) * (T(1) - w2 / T(42))) : sw / w;
-      T s2u, c2u, su, cu;
-      sincos_r<T>(T(2) * u, &s2u, &c2u);
-      sincos_r<T>(u, &su, &cu);
-      // e^{-iu} = cu - i su
-      // h0 = (u2 - w2) e^{2iu} + e^{-iu} (8 u2 cw + 2 i u (3 u2 + w2) xi0)
-      T br = T(8) * u2 * cw, bi = T(2) * u * (T(3) * u2 + w2) * xi0;
-      T h0r = (u2 - w2) * c2u + (cu * br + su * bi);
-      T h0i = (u2 - w2) * s2u + (cu * bi - su * br);
-      // h1 = 2u e^{2iu} - e^{-iu} (2u cw - i (3u2 - w2) xi0)
-      br = T(2) * u * cw; bi = -(T(3) * u2 - w2) * xi0;
-      T h1r = T(2) * u * c2u - (cu * br + su * bi);
-      T h1i = T(2) * u * s2u - (cu * bi - su * br);
-      // h2 = e^{2iu} - e^{-iu} (cw + 3 i u xi0)
-      br = cw; bi = T(3) * u * xi0;
-      T h2r = c2u - (cu * br + su * bi);
-      T h2i = s2u - (cu * bi - su * br);
-      T inv = T(1) / (T(9) * u2 - w2);
-      f0r = h0r * inv; f0i = h0i * inv;
-      f1r = h1r * inv; f1i = h1i * inv;
-      f2r = h2r * inv; f2i = h2i * inv;
-      if (neg) {  // f_j(-c0) = (-1)^j conj(f_j(c0))
-        f0i = -f0i;
-        f1r = -f1r;
-        f2i = -f2i;
-      }
+    const T c0 = trq3 / T(3);
+    // scaling: k halvings bring the spectral radius bound below 1/2
+    T r2 = T(4) / T(3) * c1;       // bound on the squared spectral radius
+    int k = 0;
+    T sc = T(1);
+    while (r2 > T(0.25)) { r2 *= T(0.25); sc *= T(0.5); ++k; }
+    const T c0k = c0 * sc * sc * sc, c1k = c1 * sc * sc;
+    // series of exp(i Q_k), Q_k^n = a + b Q_k + c Q_k^2
+    constexpr int NT = sizeof(T) == 8 ? 14 : 8;
+    T a = T(1), b = T(0), c = T(0);
+    T g0r = T(1), g0i = T(0), g1r = T(0), g1i = T(0), g2r = T(0), g2i = T(0);
+    T w = T(1);
+#pragma unroll
+    for (int n = 1; n <= NT; ++n) {
+      const T an = c0k * c, bn = a + c1k * c, cn = b;
+      a = an; b = bn; c = cn;
+      w /= T(n);
+      // i^n: 1, i, -1, -i
+      if ((n & 3) == 0) { g0r += w * a; g1r += w * b; g2r += w * c; }
+      else if ((n & 3) == 1) { g0i += w * a; g1i += w * b; g2i += w * c; }
+      else if ((n & 3) == 2) { g0r -= w * a; g1r -= w * b; g2r -= w * c; }
+      else { g0i -= w * a; g1i -= w * b; g2i -= w * c; }
     }
-    Link r;
+    // coefficients with respect to Q
+    T h0r = g0r, h0i = g0i, h1r = g1r * sc, h1i = g1i * sc, h2r = g2r * sc * sc, h2i = g2i * sc * sc;
+    for (int q = 0; q < k; ++q) {
+      // n0 = h0^2 + 2 h1 h2 c0, n1 = 2 h0 h1 + 2 h1 h2 c1 + h2^2 c0, n2 = h1^2 + 2 h0 h2 + h2^2 c1
+      const T h00r = h0r * h0r - h0i * h0i, h00i = T(2) * h0r * h0i;
+      const T h12r = h1r * h2r - h1i * h2i, h12i = h1r * h2i + h1i * h2r;
+      const T h01r = h0r * h1r - h0i * h1i, h01i = h0r * h1i + h0i * h1r;
+      const T h22r = h2r * h2r - h2i * h2i, h22i = T(2) * h2r * h2i;
+      const T h11r = h1r * h1r - h1i * h1i, h11i = T(2) * h1r * h1i;
+      const T h02r = h0r * h2r - h0i * h2i, h02i = h0r * h2i + h0i * h2r;
+      h0r = h00r + T(2) * c0 * h12r; h0i = h00i + T(2) * c0 * h12i;
+      h1r = T(2) * h01r + T(2) * c1 * h12r + c0 * h22r; h1i = T(2) * h01i + T(2) * c1 * h12i + c0 * h22i;
+      h2r = h11r + T(2) * h02r + c1 * h22r; h2i = h11i + T(2) * h02i + c1 * h22i;
+    }
+    Link R;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        T qr = Q.re[i][j], qi = Q.im[i][j], pr = Q2.re[i][j], pi = Q2.im[i][j];
-        r.re[i][j] = f1r * qr - f1i * qi + f2r * pr - f2i * pi;
-        r.im[i][j] = f1r * qi + f1i * qr + f2r * pi + f2i * pr;
+        const T qr = Q.re[i][j], qi = Q.im[i][j], pr = Q2.re[i][j], pi = Q2.im[i][j];
+        R.re[i][j] = h1r * qr - h1i * qi + h2r * pr - h2i * pi;
+        R.im[i][j] = h1r * qi + h1i * qr + h2r * pi + h2i * pr;
       }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { r.re[i][i] += f0r; r.im[i][i] += f0i; }
-    return r;
+    for (int i = 0; i < 3; ++i) { R.re[i][i] += h0r; R.im[i][i] += h0i; }
+    return R;
   }
   // U^dag X U
   static GL_HD Alg transport(const Link& u, const Alg& x) {

@@ -1,18 +1,16 @@
 // Lattice geometry and tiled structure-of-arrays field access.
 //
 // Site index s = (z * nt + y) * nt + x, x fastest, so a wavefront of 64 lanes reads
-// 64 consecutive x.  Fields are stored per direction as arrays of records: the sites
-// are grouped in blocks of B = 128 / sizeof(real) consecutive sites (16 in double,
-// 32 in float) and a record holds, for one block, each real component as a row of
-// B values (one 128-byte line).  A wavefront reading component c of 64 consecutive
-// sites touches whole 128-byte lines, and all components of one site are at fixed
-// offsets c * 128 bytes from the site's address, so one 64-bit address per
-// (site, direction) serves every component through immediate offsets.
-//   links  direction i: record width R (SU(2): 4 quaternion reals; SU(3): 18 reals,
+// 64 consecutive x.  Each field direction is an array of records of 64 consecutive
+// sites; inside a record the real components are grouped in 16-byte chunks, one row
+// of 64 chunks per group (see the record access below), so every lane fetches a
+// link or an algebra element with few 16-byte loads and a wavefront's load covers a
+// contiguous 1 KiB.
+//   links  direction i: width R (SU(2): 4 quaternion reals; SU(3): 18 reals,
 //          c = 2 (3 r + k) + {0 re, 1 im})
-//   E      direction i: record width NG (algebra components E^a = 2 Tr(t^a E))
-//   rho    record width NG
-// The site count is padded to Vp (a multiple of 32) and direction i of a field
+//   E      direction i: width NG (algebra components E^a = 2 Tr(t^a E))
+//   rho    width NG
+// The site count is padded to Vp (a multiple of 64) and direction i of a field
 // starts at element i * Vp * width.  All three lattice directions are periodic.
 #pragma once
 #include <stdint.h>
@@ -23,11 +21,11 @@ namespace gl {
 struct Geom {
   int nt, nz;
   int64_t V;     // nt * nt * nz
-  int64_t Vp;    // V rounded up to a multiple of 32 (record padding)
+  int64_t Vp;    // V rounded up to a multiple of 64 (record padding)
   int64_t layer; // nt * nt
 };
 
-constexpr int VPAD = 32;
+constexpr int VPAD = 64;
 GL_HD int64_t padded_sites(int64_t V) { return (V + VPAD - 1) / VPAD * VPAD; }
 
 GL_HD int wrap_add(int v, int d, int n) {
@@ -57,75 +55,168 @@ GL_HD Site shifted(const Geom& g, Site s, int i, int d) {
 GL_HD uint32_t idx(const Geom& g, Site s) { return site_index(g, s.x, s.y, s.z); }
 
 // ---- tiled record access ----------------------------------------------------
+// A record holds RB = 64 consecutive sites of one direction.  Inside a record the
+// components are grouped in 16-byte chunks (4 floats or 2 doubles): chunk row q
+// stores components [q VW, q VW + VW) of all 64 sites, 16 bytes per site, so one
+// 16-byte load per lane fetches VW components and a wavefront reads a contiguous
+// 1 KiB row.  Components left over (W mod VW) form a last, narrower row.
+constexpr int RB = 64;
 template <typename S> struct Rec {
-  static constexpr int B = 128 / (int)sizeof(S);          // sites per block
-  static constexpr int LOGB = sizeof(S) == 8 ? 4 : 5;
+  static constexpr int VW = 16 / (int)sizeof(S);          // components per 16-byte chunk
 };
-// byte offset of site s inside one direction's array of records of width W
-template <typename S, int W> GL_HD uint64_t rec_off(uint32_t s) {
-  return (uint64_t)(s >> Rec<S>::LOGB) * (uint64_t)(W * 128) + (uint64_t)((s & (Rec<S>::B - 1)) * sizeof(S));
-}
-// element index of (direction-local component c, site s) for width W (host transfers)
+template <typename S, int W> struct RecShape {
+  static constexpr int VW = Rec<S>::VW;
+  static constexpr int NF = W / VW;                        // full 16-byte rows
+  static constexpr int TL = W % VW;                        // components in the last row
+  static constexpr uint32_t BYTES = RB * W * sizeof(S);   // record size
+};
+// element index of (component c, site s) in one direction's array of width W (host transfers)
 template <typename S> GL_HD int64_t rec_elem(int64_t s, int c, int W) {
-  return (s >> Rec<S>::LOGB) * (int64_t)(W * Rec<S>::B) + (int64_t)c * Rec<S>::B + (s & (Rec<S>::B - 1));
+  const int VW = Rec<S>::VW, nf = W / VW, tl = W % VW;
+  const int64_t rec = (s / RB) * (int64_t)RB * W;
+  const int l = (int)(s % RB);
+  if (c < nf * VW) return rec + (int64_t)(c / VW) * RB * VW + (int64_t)l * VW + c % VW;
+  return rec + (int64_t)nf * RB * VW + (int64_t)l * tl + (c - nf * VW);
 }
 
 template <typename S> GL_HD const S* field_dir(const S* f, int i, int W, int64_t Vp) { return f + (int64_t)i * Vp * W; }
 template <typename S> GL_HD S* field_dir(S* f, int i, int W, int64_t Vp) { return f + (int64_t)i * Vp * W; }
 
-template <typename S> GL_HD const S& at(const char* p, int c) { return *(const S*)(p + c * 128); }
-template <typename S> GL_HD S& at(char* p, int c) { return *(S*)(p + c * 128); }
+template <typename S> struct Vec16;
+template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double2; };
+
+// load / store the W components of site s from one direction's record array
+template <typename T, typename S, int W>
+GL_HD void load_comps(T (&v)[W], const S* __restrict__ dir, uint32_t s) {
+  using Sh = RecShape<S, W>;
+  using V16 = typename Vec16<S>::type;
+  const char* rec = (const char*)dir + (uint64_t)(s / RB) * Sh::BYTES;
+  const uint32_t l = s % RB;
+#pragma unroll
+  for (int q = 0; q < Sh::NF; ++q) {
+    const V16 x = *(const V16*)(rec + q * (RB * 16) + l * 16);
+    const S* e = (const S*)&x;
+#pragma unroll
+    for (int k = 0; k < Sh::VW; ++k) v[q * Sh::VW + k] = (T)e[k];
+  }
+  if constexpr (Sh::TL > 0) {
+    const S* t = (const S*)(rec + Sh::NF * (RB * 16) + l * (Sh::TL * sizeof(S)));
+#pragma unroll
+    for (int k = 0; k < Sh::TL; ++k) v[Sh::NF * Sh::VW + k] = (T)t[k];
+  }
+}
+template <typename T, typename S, int W>
+GL_HD void store_comps(const T (&v)[W], S* __restrict__ dir, uint32_t s) {
+  using Sh = RecShape<S, W>;
+  using V16 = typename Vec16<S>::type;
+  char* rec = (char*)dir + (uint64_t)(s / RB) * Sh::BYTES;
+  const uint32_t l = s % RB;
+#pragma unroll
+  for (int q = 0; q < Sh::NF; ++q) {
+    V16 x;
+    S* e = (S*)&x;
+#pragma unroll
+    for (int k = 0; k < Sh::VW; ++k) e[k] = (S)v[q * Sh::VW + k];
+    *(V16*)(rec + q * (RB * 16) + l * 16) = x;
+  }
+  if constexpr (Sh::TL > 0) {
+    S* t = (S*)(rec + Sh::NF * (RB * 16) + l * (Sh::TL * sizeof(S)));
+#pragma unroll
+    for (int k = 0; k < Sh::TL; ++k) t[k] = (S)v[Sh::NF * Sh::VW + k];
+  }
+}
 
 // ---- link load / store (storage type S, compute type T); Vp = padded site count --
 template <typename T, typename S>
 GL_HD void load_link(Q2<T>& l, const S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  const char* p = (const char*)field_dir(U, i, 4, Vp) + rec_off<S, 4>(s);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) l.q[c] = (T)at<S>(p, c);
+  load_comps<T, S, 4>(l.q, field_dir(U, i, 4, Vp), s);
 }
 template <typename T, typename S>
 GL_HD void store_link(const Q2<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  char* p = (char*)field_dir(U, i, 4, Vp) + rec_off<S, 4>(s);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) at<S>(p, c) = (S)l.q[c];
+  store_comps<T, S, 4>(l.q, field_dir(U, i, 4, Vp), s);
 }
 template <typename T, typename S>
 GL_HD void load_link(M3<T>& l, const S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  const char* p = (const char*)field_dir(U, i, 18, Vp) + rec_off<S, 18>(s);
+  T v[18];
+  load_comps<T, S, 18>(v, field_dir(U, i, 18, Vp), s);
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      l.re[r][k] = (T)at<S>(p, 2 * (3 * r + k));
-      l.im[r][k] = (T)at<S>(p, 2 * (3 * r + k) + 1);
+      l.re[r][k] = v[2 * (3 * r + k)];
+      l.im[r][k] = v[2 * (3 * r + k) + 1];
     }
 }
 template <typename T, typename S>
 GL_HD void store_link(const M3<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  char* p = (char*)field_dir(U, i, 18, Vp) + rec_off<S, 18>(s);
+  T v[18];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      at<S>(p, 2 * (3 * r + k)) = (S)l.re[r][k];
-      at<S>(p, 2 * (3 * r + k) + 1) = (S)l.im[r][k];
+      v[2 * (3 * r + k)] = l.re[r][k];
+      v[2 * (3 * r + k) + 1] = l.im[r][k];
     }
+  store_comps<T, S, 18>(v, field_dir(U, i, 18, Vp), s);
 }
 
 // ---- algebra load / store: f = field base, i = direction (0 for rho) ----------
 template <typename A, typename S>
 GL_HD void load_alg(A& a, const S* __restrict__ f, int i, uint32_t s, int64_t Vp) {
   constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
-  const char* p = (const char*)field_dir(f, i, NG, Vp) + rec_off<S, NG>(s);
-#pragma unroll
-  for (int k = 0; k < NG; ++k) a.c[k] = (decltype(a.c[0] + 0))at<S>(p, k);
+  load_comps<decltype(a.c[0] + 0), S, NG>(a.c, field_dir(f, i, NG, Vp), s);
 }
 template <typename A, typename S>
 GL_HD void store_alg(const A& a, S* __restrict__ f, int i, uint32_t s, int64_t Vp) {
   constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
-  char* p = (char*)field_dir(f, i, NG, Vp) + rec_off<S, NG>(s);
-#pragma unroll
-  for (int k = 0; k < NG; ++k) at<S>(p, k) = (S)a.c[k];
+  store_comps<decltype(a.c[0] + 0), S, NG>(a.c, field_dir(f, i, NG, Vp), s);
+}
+
+// Work-group placement: the hardware hands work-groups to the 8 XCDs round-robin
+// (b mod 8), and each XCD has its own L2.  Renumbering so that XCD k receives one
+// contiguous range of blocks keeps the y and z neighbours of a block in the same L2.
+// The map is a bijection of [0, nb) for any nb.
+constexpr int NXCD = 8;
+GL_HD uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  const uint32_t q = nb / NXCD, r = nb % NXCD, x = b % NXCD;
+  return x * q + (x < r ? x : r) + b / NXCD;
+}
+
+// Column decomposition of the lattice over the XCDs: XCD k owns a contiguous range of
+// transverse rows y for every z and sweeps it layer by layer, so the links a block
+// loads as z + 1 neighbours are read again, as z and z - 1, by the blocks that follow
+// on the same XCD while they are still in its L2; rows are x-contiguous, so only the
+// y halo of the row range crosses XCDs.  Work-group b runs on XCD b mod 8 and covers
+// BS consecutive sites of one (z, row range) segment; blocks past a segment's end idle.
+struct ColMap {
+  int r0, rem;   // rows per XCD: r0 + (k < rem)
+  int bt;        // blocks per (XCD, layer)
+};
+inline ColMap col_map(const Geom& g, int bs) {
+  ColMap m;
+  m.r0 = g.nt / NXCD;
+  m.rem = g.nt % NXCD;
+  const int64_t maxrows = m.r0 + (m.rem > 0 ? 1 : 0);
+  m.bt = (int)((maxrows * g.nt + bs - 1) / bs);
+  return m;
+}
+inline uint32_t col_map_blocks(const Geom& g, const ColMap& m) { return (uint32_t)NXCD * g.nz * m.bt; }
+// site of thread t in block b, or false when the thread has no site
+GL_HD bool col_map_site(const Geom& g, const ColMap& m, uint32_t b, uint32_t t, uint32_t bs, Site& x, uint32_t& s) {
+  const int k = (int)(b % NXCD);
+  const uint32_t j = b / NXCD;
+  const int z = (int)(j / (uint32_t)m.bt);
+  const uint32_t ch = j % (uint32_t)m.bt;
+  const int nrows = m.r0 + (k < m.rem ? 1 : 0);
+  const int start = k * m.r0 + (k < m.rem ? k : m.rem);
+  const uint32_t local = ch * bs + t;
+  if (z >= g.nz || local >= (uint32_t)nrows * (uint32_t)g.nt) return false;
+  x.y = start + (int)(local / (uint32_t)g.nt);
+  x.x = (int)(local % (uint32_t)g.nt);
+  x.z = z;
+  s = site_index(g, x.x, x.y, x.z);
+  return true;
 }
 
 // Per-step constants shared by the kernels.

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
       L S = staple_sum<G, T>(U, g, x, i, inv_a2);
       L Ui;
       load_link(Ui, U, i, s, Vp);
-      A f = G::proj(G::mul(Ui, S));
+      A f = G::proj_mul(Ui, S);
       A eo, en;
       load_alg(eo, E, i, s, Vp);
       for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k] - c.dt / c.a[i] * f.c[k];
@@ -219,10 +219,14 @@ __global__ void k_current(const T* __restrict__ U, const T* __restrict__ rhoA, c
     const typename G::Real k = (typename G::Real)(c.a[2] / c.dt);
     for (int q = 0; q < NG; ++q) jz.c[q] = k * (ran.c[q] - rb.c[q]);
   }
-  A zero = G::alg_zero();
-  store_alg(zero, j, 0, s, Vp);
-  store_alg(zero, j, 1, s, Vp);
-  store_alg(jz, j, 2, s, Vp);
+  // plain structure-of-arrays output j[(i * NG + a) * V + s]
+  const int64_t V = g.V;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    j[(int64_t)q * V + s] = T(0);
+    j[(int64_t)(NG + q) * V + s] = T(0);
+    j[(int64_t)(2 * NG + q) * V + s] = (T)jz.c[q];
+  }
 }
 
 template <typename G, typename T>

@@ -31,7 +31,7 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
   L S = staple_sum<G, T>(U, g, x, i, inv_a2);
   L Ui;
   load_link(Ui, U, i, s, Vp);
-  A f = G::proj(G::mul(Ui, S));
+  A f = G::proj_mul(Ui, S);
   A e;
   load_alg(e, E, i, s, Vp);
   const T kf = (T)(-c.dt / c.a[i]);
@@ -68,13 +68,11 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
 template <typename G, typename T, bool HOP>
 __global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
                                                                T* __restrict__ E, T* __restrict__ rhoA,
-                                                               T* __restrict__ rhoB, Geom g, StepConst c) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= (uint32_t)g.V) return;
+                                                               T* __restrict__ rhoB, Geom g, StepConst c,
+                                                               ColMap m) {
   Site x;
-  x.x = (int)(s % (uint32_t)g.nt);
-  x.y = (int)((s / (uint32_t)g.nt) % (uint32_t)g.nt);
-  x.z = (int)(s / (uint32_t)g.layer);
+  uint32_t s;
+  if (!col_map_site(g, m, blockIdx.x, threadIdx.x, blockDim.x, x, s)) return;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
 #pragma unroll 1
   for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
@@ -85,7 +83,7 @@ template <typename G, typename T, bool HOP>
 __global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog_dir(const T* __restrict__ U, T* __restrict__ Unew,
                                                                    T* __restrict__ E, T* __restrict__ rhoA,
                                                                    T* __restrict__ rhoB, Geom g, StepConst c) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= (uint32_t)g.V) return;
   Site x;
   x.x = (int)(s % (uint32_t)g.nt);
@@ -107,10 +105,12 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
     else
       hipLaunchKernelGGL((k_leapfrog_dir<G, T, false>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
   } else {
+    const ColMap m = col_map(g, bs);
+    const unsigned nbc = col_map_blocks(g, m);
     if (c.hop)
-      hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+      hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
     else
-      hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3((unsigned)nb), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+      hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
   }
 }
 
