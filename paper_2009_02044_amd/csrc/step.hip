@@ -57,11 +57,49 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
   store_link(Un, Unew, i, s, Vp);
 }
 
+// Update of link (x, i) from its staple sum S (the z-link thread also hops the charges).
+template <typename G, typename T, bool HOP>
+__device__ __forceinline__ void finish_link(T* __restrict__ Unew, T* __restrict__ E, T* __restrict__ rhoA,
+                                            T* __restrict__ rhoB, const Geom& g, const StepConst& c, Site x,
+                                            uint32_t s, int i, const typename G::Link& Ui,
+                                            const typename G::Link& S) {
+  using L = typename G::Link;
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t Vp = g.Vp;
+  A f = G::proj_mul(Ui, S);
+  A e;
+  load_alg(e, E, i, s, Vp);
+  const T kf = (T)(-c.dt / c.a[i]);
+#pragma unroll
+  for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
+  if (HOP && i == 2) {
+    const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
+    const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
+    A rb, ra;
+    load_alg(rb, rhoB, 0, sB, Vp);
+    load_alg(ra, rhoA, 0, sA, Vp);
+    A rbn = G::transport(Ui, rb);
+    A ran = G::transport_inv(Ui, ra);
+    store_alg(rbn, rhoB, 0, sB, Vp);
+    store_alg(ran, rhoA, 0, sA, Vp);
+    const T al = (T)c.a[2];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
+  }
+  store_alg(e, E, i, s, Vp);
+  L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
+  store_link(Un, Unew, i, s, Vp);
+}
+
 #ifndef GL_LF_WAVES
 #define GL_LF_WAVES 1
 #endif
 #ifndef GL_LF_PER_DIR
 #define GL_LF_PER_DIR 0
+#endif
+#ifndef GL_LF_PAIRS
+#define GL_LF_PAIRS 0
 #endif
 
 // One thread per site, the three directions in turn.
@@ -76,6 +114,25 @@ __global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog(const T* __restri
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
 #pragma unroll 1
   for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
+}
+
+// One thread per site, staple sums of all three directions by unordered planes.
+template <typename G, typename T, bool HOP>
+__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog_pairs(const T* __restrict__ U, T* __restrict__ Unew,
+                                                                     T* __restrict__ E, T* __restrict__ rhoA,
+                                                                     T* __restrict__ rhoB, Geom g, StepConst c,
+                                                                     ColMap m) {
+  using L = typename G::Link;
+  Site x;
+  uint32_t s;
+  if (!col_map_site(g, m, blockIdx.x, threadIdx.x, blockDim.x, x, s)) return;
+  const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
+  L Ux[3], S[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) load_link(Ux[i], U, i, s, g.Vp);
+  staple_sums_pairs<G, T>(U, g, x, Ux, inv_a2, S);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) finish_link<G, T, HOP>(Unew, E, rhoA, rhoB, g, c, x, s, i, Ux[i], S[i]);
 }
 
 // One thread per link: direction i = blockIdx.y, uniform over the block.
@@ -104,6 +161,13 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
       hipLaunchKernelGGL((k_leapfrog_dir<G, T, true>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
     else
       hipLaunchKernelGGL((k_leapfrog_dir<G, T, false>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
+  } else if (GL_LF_PAIRS) {
+    const ColMap m = col_map(g, bs);
+    const unsigned nbc = col_map_blocks(g, m);
+    if (c.hop)
+      hipLaunchKernelGGL((k_leapfrog_pairs<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+    else
+      hipLaunchKernelGGL((k_leapfrog_pairs<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
   } else {
     const ColMap m = col_map(g, bs);
     const unsigned nbc = col_map_blocks(g, m);
