@@ -161,6 +161,9 @@ int glasma_get_state(glasma_ctx* ctx, double* U, double* E, double* rhoA, double
  * Gram-Schmidt of rows 1, 2, row 3 = conj(r1 x r2)).  Asynchronous. */
 int glasma_reunitarize(glasma_ctx* ctx);
 
+/* Fixed-point iterations used by the last semi-implicit step (host value). */
+int glasma_last_iterations(const glasma_ctx* ctx, int32_t* iters);
+
 /* Current step counter (host value). */
 int glasma_get_step(const glasma_ctx* ctx, int64_t* step);
 

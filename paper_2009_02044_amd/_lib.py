@@ -62,6 +62,7 @@ def _load():
         "glasma_get_state": ([P, D, D, D, D, C.POINTER(I64)], C.c_int),
         "glasma_reunitarize": ([P], C.c_int),
         "glasma_get_step": ([P, C.POINTER(I64)], C.c_int),
+        "glasma_last_iterations": ([P, C.POINTER(I32)], C.c_int),
         "glasma_host_group_op": ([I32, I32, I32, I64, D, D], C.c_int),
     }
     for name, (args, res) in sig.items():

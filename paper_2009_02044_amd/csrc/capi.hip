@@ -22,6 +22,7 @@ struct glasma_ctx {
   int offA, offB;     // co-moving charge storage offsets (mod nz)
   int64_t hop_p, hop_q;  // dt / a_L = hop_p / hop_q
   bool ready;
+  int last_iters;     // iterations of the last semi-implicit step
   std::string err;
 };
 
@@ -83,13 +84,36 @@ static Geom geom_of(const glasma_params* p) {
   return g;
 }
 
-static size_t work_doubles(const glasma_params* p) {
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Work buffer: [general region: initial conditions or observable reductions]
+// then, for the semi-implicit scheme, [U(t-dt) | trial links | trial E | f1(U(t), U(t-dt)) | dt j | 2 doubles].
+struct SemiRegion {
+  size_t up, ut, et, f2, j, conv, end;  // byte offsets
+};
+static size_t general_bytes(const glasma_params* p) {
   Geom g = geom_of(p);
   int ng = p->nc * p->nc - 1;
   size_t ic = ic_work_doubles(g, ng);
   size_t obs = observe_partial_doubles(g) + 4 * (size_t)g.nz + GLASMA_OBS_NSCALARS;
-  size_t w = ic > obs ? ic : obs;
-  return w;
+  return align256((ic > obs ? ic : obs) * sizeof(double));
+}
+static SemiRegion semi_region(const glasma_params* p) {
+  Geom g = geom_of(p);
+  const size_t e = p->fp == 64 ? 8 : 4;
+  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  SemiRegion s;
+  s.up = general_bytes(p);
+  s.ut = s.up + align256(3 * (size_t)r * g.Vp * e);
+  s.et = s.ut + align256(3 * (size_t)r * g.Vp * e);
+  s.f2 = s.et + align256(3 * (size_t)ng * g.Vp * e);
+  s.j = s.f2 + align256(3 * (size_t)ng * g.Vp * e);
+  s.conv = s.j + align256((size_t)ng * g.Vp * e);
+  s.end = s.conv + 256;
+  return s;
+}
+static size_t work_bytes(const glasma_params* p) {
+  return p->scheme == 1 ? semi_region(p).end : general_bytes(p);
 }
 
 template <class F> static int dispatch(glasma_ctx* c, F&& f) {
@@ -106,6 +130,7 @@ static StepConst step_const(const glasma_ctx* c) {
   k.hop = is_hop(c, c->step) ? 1 : 0;
   k.offA = c->offA;
   k.offB = c->offB;
+  k.scheme = c->p.scheme;
   return k;
 }
 
@@ -130,7 +155,7 @@ int glasma_layout(const glasma_params* p, size_t* bytes) {
   bytes[2] = 3 * (size_t)ng * g.Vp * e;
   bytes[3] = (size_t)ng * g.Vp * e;
   bytes[4] = bytes[3];
-  bytes[5] = work_doubles(p) * sizeof(double);
+  bytes[5] = work_bytes(p);
   return GLASMA_OK;
 }
 
@@ -141,7 +166,8 @@ int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream,
   if (!b || !out) return fail(nullptr, GLASMA_E_ARG, "buffers or out is NULL");
   if (!b->U || !b->U_alt || !b->E || !b->rhoA || !b->rhoB || !b->work)
     return fail(nullptr, GLASMA_E_ARG, "a device buffer is NULL");
-  if (p->scheme == 1) return fail(nullptr, GLASMA_E_ARG, "scheme 1 is not available in this build");
+  if (p->scheme == 1 && (p->max_iter < 1 || !(p->tol > 0)))
+    return fail(nullptr, GLASMA_E_ARG, "the semi-implicit scheme needs max_iter >= 1 and tol > 0");
   glasma_ctx* c = new glasma_ctx();
   c->p = *p;
   c->b = *b;
@@ -155,12 +181,19 @@ int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream,
   c->hop_p = hp;
   c->hop_q = hq;
   c->ready = false;
+  c->last_iters = 0;
   *out = c;
   return GLASMA_OK;
 }
 
 int glasma_destroy(glasma_ctx* ctx) {
   delete ctx;
+  return GLASMA_OK;
+}
+
+int glasma_last_iterations(const glasma_ctx* ctx, int32_t* iters) {
+  if (!ctx || !iters) return fail(nullptr, GLASMA_E_ARG, "NULL argument");
+  *iters = ctx->last_iters;
   return GLASMA_OK;
 }
 
@@ -223,11 +256,61 @@ int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, con
   dispatch(c, [&]<typename G, typename T>() -> int {
     launch_init_mv<G, T>(work, work, (T*)c->b.U, (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, k,
                          c->stream);
+    if (c->p.scheme == 1) {
+      // charges that make the conserved combination D.(E + dt f1(U(t0), U(t0 - dt))) - rho vanish
+      const SemiRegion r = semi_region(&c->p);
+      char* w = (char*)c->b.work;
+      launch_semi_begin<G, T>((T*)c->b.U, (T*)c->b.E, (T*)(w + r.up), (T*)(w + r.ut), (T*)(w + r.et), c->g, sc,
+                              c->stream);
+      launch_semi_f1<G, T>((T*)c->b.U, (T*)(w + r.up), (T*)(w + r.f2), c->g, sc, c->stream);
+      launch_gauss_charges<G, T>((T*)c->b.U, (T*)c->b.E, (T*)(w + r.f2), c->p.dt, (T*)c->b.rhoA,
+                                 (T*)c->b.rhoB, c->g, sc, c->stream);
+    }
     return 0;
   });
   HIPCHK(c, hipGetLastError());
   c->ready = true;
   return GLASMA_OK;
+}
+
+// One semi-implicit step: U(t - dt), f1(U(t), U(t - dt)) and the hop once, then fixed-point
+// iterations on E(t + dt/2) until max|dE| <= tol max|E|; the new links end in next_U.
+static int semi_step(glasma_ctx* c, const StepConst& sc) {
+  const SemiRegion r = semi_region(&c->p);
+  char* w = (char*)c->b.work;
+  double* conv = (double*)(w + r.conv);
+  double h[2];
+  return dispatch(c, [&]<typename G, typename T>() -> int {
+    T* Uc = cur_U<T>(c);
+    T* Un = next_U<T>(c);
+    T* Up = (T*)(w + r.up);
+    T* Ub = (T*)(w + r.ut);
+    T* Et = (T*)(w + r.et);
+    T* F2 = (T*)(w + r.f2);
+    T* J = (T*)(w + r.j);
+    launch_semi_begin<G, T>(Uc, (T*)c->b.E, Up, Un, Et, c->g, sc, c->stream);
+    if (sc.hop) launch_semi_hop<G, T>(Uc, (T*)c->b.rhoA, (T*)c->b.rhoB, J, c->g, sc, c->stream);
+    launch_semi_f1<G, T>(Uc, Up, F2, c->g, sc, c->stream);
+    T* in = Un;
+    T* out = Ub;
+    bool ok = false;
+    for (int it = 0; it < c->p.max_iter; ++it) {
+      HIPCHK(c, hipMemsetAsync(conv, 0, 2 * sizeof(double), c->stream));
+      launch_semi_iter<G, T>(Uc, in, (T*)c->b.E, F2, J, Et, out, conv, c->g, sc, c->stream);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(h, conv, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      T* t = in; in = out; out = t;
+      c->last_iters = it + 1;
+      if (!(h[0] == h[0]) || !(h[1] == h[1])) return fail(c, GLASMA_E_NONFINITE, "non-finite field in the semi-implicit solve");
+      if (h[0] <= c->p.tol * (h[1] > 0 ? h[1] : 1e-300)) { ok = true; break; }
+    }
+    if (!ok) return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");
+    const int64_t nl = 3 * (int64_t)c->r * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
+    if (in != Un) launch_copy<G, T>(in, Un, nl, c->stream);
+    launch_copy<G, T>(Et, (T*)c->b.E, ne, c->stream);
+    return GLASMA_OK;
+  });
 }
 
 int glasma_step(glasma_ctx* c, int32_t n) {
@@ -236,11 +319,16 @@ int glasma_step(glasma_ctx* c, int32_t n) {
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state: call glasma_init_state or glasma_init_mv first");
   for (int32_t k = 0; k < n; ++k) {
     StepConst sc = step_const(c);
-    dispatch(c, [&]<typename G, typename T>() -> int {
-      launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
-                            c->stream);
-      return 0;
-    });
+    if (c->p.scheme == 1) {
+      int rc = semi_step(c, sc);
+      if (rc) return rc;
+    } else {
+      dispatch(c, [&]<typename G, typename T>() -> int {
+        launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
+                              c->stream);
+        return 0;
+      });
+    }
     c->cur ^= 1;
     if (sc.hop) {
       c->offA = (c->offA + 1) % c->g.nz;

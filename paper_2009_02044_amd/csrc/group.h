@@ -82,6 +82,10 @@ template <typename T> struct Su2 {
   // pure quaternion i X = (0, x/2)
   static GL_HD Link alg_as_link(const Alg& x) { Link r; r.q[0] = 0; r.q[1] = x.c[0] / 2; r.q[2] = x.c[1] / 2; r.q[3] = x.c[2] / 2; return r; }
   static GL_HD Alg link_as_alg(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
+  // Hermitian traceless matrices M are carried as i M, which lies in the real span of
+  // SU(2) (a pure quaternion), so the Link type and its products serve for them too.
+  static GL_HD Link herm_from_alg(const Alg& x) { return alg_as_link(x); }
+  static GL_HD Alg alg_from_herm(const Link& m) { return link_as_alg(m); }
   // U^dag X U
   static GL_HD Alg transport(const Link& u, const Alg& x) { return link_as_alg(mul(dag_mul(u, alg_as_link(x)), u)); }
   // U X U^dag
@@ -252,6 +256,9 @@ template <typename T> struct Su3 {
     q.re[2][1] = h * x.c[5]; q.im[2][1] = h * x.c[6];
     return q;
   }
+  // hermitian matrices are carried as themselves (3x3 complex)
+  static GL_HD Link herm_from_alg(const Alg& x) { return herm(x, T(1)); }
+  static GL_HD Alg alg_from_herm(const Link& m) { return alg_of_herm(m); }
   // components of a hermitian traceless matrix
   static GL_HD Alg alg_of_herm(const Link& q) {
     const T is3 = T(0.57735026918962576451);

@@ -127,8 +127,8 @@ __global__ void k_ic_links(const double* __restrict__ phi, T* __restrict__ U, T*
 }
 
 template <typename Gd, typename T>
-__global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, T* __restrict__ rhoA,
-                           T* __restrict__ rhoB, Geom g, StepConst c) {
+__global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, const T* __restrict__ F2,
+                           double scale, T* __restrict__ rhoA, T* __restrict__ rhoB, Geom g, StepConst c) {
   constexpr int NG = Gd::NG;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
@@ -143,6 +143,12 @@ __global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, T* 
     typename Gd::Alg eh, em;
     load_alg(eh, E, i, s, Vp);
     load_alg(em, E, i, sm, Vp);
+    if (F2) {
+      typename Gd::Alg fh, fm;
+      load_alg(fh, F2, i, s, Vp);
+      load_alg(fm, F2, i, sm, Vp);
+      for (int q = 0; q < NG; ++q) { eh.c[q] += scale * fh.c[q]; em.c[q] += scale * fm.c[q]; }
+    }
     typename Gd::Alg tr = Gd::transport(Um, em);
     for (int q = 0; q < NG; ++q) r.c[q] += (eh.c[q] - tr.c[q]) / c.a[i];
   }
@@ -169,9 +175,27 @@ void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T
   hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, phi, g.nt, nb, 3, c.a[0], mv.m_ir, mv.uv_cut);
   const unsigned sb = (unsigned)((g.V + bs - 1) / bs);
   hipLaunchKernelGGL((k_ic_links<Gd, T>), dim3(sb), dim3(bs), 0, st, phi, U, E, g, c, mv);
-  hipLaunchKernelGGL((k_ic_gauss<Gd, T>), dim3(sb), dim3(bs), 0, st, U, E, rhoA, rhoB, g, c);
+  // the semi-implicit scheme conserves D.(E + dt f1(U(t0), U(t0 - dt))) - rho instead;
+  // its caller builds f1 and sets the charges through launch_gauss_charges
+  if (c.scheme == 1) return;
+  hipLaunchKernelGGL((k_ic_gauss<Gd, T>), dim3(sb), dim3(bs), 0, st, U, E, (const T*)nullptr, 0.0, rhoA, rhoB, g, c);
 }
 
+template <typename G, typename T>
+void launch_gauss_charges(const T* U, const T* E, const T* F2, double scale, T* rhoA, T* rhoB, const Geom& g,
+                          const StepConst& c, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int bs = 256;
+  const unsigned sb = (unsigned)((g.V + bs - 1) / bs);
+  hipLaunchKernelGGL((k_ic_gauss<Gd, T>), dim3(sb), dim3(bs), 0, st, U, E, F2, scale, rhoA, rhoB, g, c);
+}
+
+#define GL_GC_INST(G, T) \
+  template void launch_gauss_charges<G, T>(const T*, const T*, const T*, double, T*, T*, const Geom&, const StepConst&, hipStream_t);
+GL_GC_INST(Su2<double>, double)
+GL_GC_INST(Su3<double>, double)
+GL_GC_INST(Su2<float>, float)
+GL_GC_INST(Su3<float>, float)
 template void launch_init_mv<Su2<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
 template void launch_init_mv<Su3<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
 template void launch_init_mv<Su2<float>, float>(const double*, double*, float*, float*, float*, float*, const Geom&, const StepConst&, const McvConst&, hipStream_t);

@@ -28,6 +28,20 @@ void launch_current(const T* U, const T* rhoA, const T* rhoB, const Geom& g, con
 template <typename G, typename T>
 void launch_reunit(T* U, const Geom& g, hipStream_t st);
 
+// Semi-implicit scheme (semi.hip)
+template <typename G, typename T>
+void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st);
+template <typename G, typename T>
+void launch_semi_begin(const T* U, const T* E, T* Up, T* Ut, T* Et, const Geom& g, const StepConst& c,
+                       hipStream_t st);
+template <typename G, typename T>
+void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, const Geom& g, const StepConst& c, hipStream_t st);
+template <typename G, typename T>
+void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
+                      double* conv, const Geom& g, const StepConst& c, hipStream_t st);
+template <typename G, typename T>
+void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
+
 // Initial conditions: rhoT_dev holds the transverse charges of both nuclei
 // (double, [2][NG][nt*nt]: A then B); work needs ic_work_doubles(g, NG) doubles.
 struct McvConst {
@@ -37,5 +51,9 @@ size_t ic_work_doubles(const Geom& g, int ng);
 template <typename G, typename T>
 void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T* rhoB,
                     const Geom& g, const StepConst& c, const McvConst& mv, hipStream_t st);
+// charges from the (modified) Gauss law: rho = D.(E + scale F2), F2 may be null; split at nz/2
+template <typename G, typename T>
+void launch_gauss_charges(const T* U, const T* E, const T* F2, double scale, T* rhoA, T* rhoB, const Geom& g,
+                          const StepConst& c, hipStream_t st);
 
 }  // namespace gl

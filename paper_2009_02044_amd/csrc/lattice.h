@@ -225,6 +225,7 @@ struct StepConst {
   double dt;
   int hop;           // 1 on a step where every charge advances one cell
   int offA, offB;    // co-moving storage offsets of the two charge populations
+  int scheme;        // 0 leapfrog, 1 semi-implicit
 };
 
 // Co-moving charge storage: nucleus B (moving +z) keeps the charge that sits at

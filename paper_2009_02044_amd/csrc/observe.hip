@@ -76,7 +76,11 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
       A eo, en;
       load_alg(eo, E, i, s, Vp);
       for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k] - c.dt / c.a[i] * f.c[k];
-      if (c.hop && i == 2) {
+      // semi-implicit scheme: E(t + dt/2) needs the next implicit solve; its
+      // observables use E(t - dt/2) for both half steps
+      if (c.scheme == 1)
+        for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k];
+      if (c.hop && i == 2 && c.scheme == 0) {
         A rb, ra;
         load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
         load_alg(ra, rhoA, 0, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), Vp);

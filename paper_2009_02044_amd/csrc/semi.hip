@@ -1,0 +1,344 @@
+// Semi-implicit scheme with time-averaged plaquette-like terms (Sec. 3, fig. wilson and
+// the text on the numerical Cherenkov instability; Sec. 5): the reading implemented
+// here replaces the Wilson potential of one time slice by a potential between two
+// neighbouring slices m, m+1 (X.Y = sum_a X^a Y^a)
+//   v(m, m+1) = k_xy P(C_xy^m) . P(C_xy^{m+1})
+//             + sum_{i=x,y} k_iz [ P(C_iz^{(m,m)}) . P(C_iz^{(m,m+1)}) + P(C_iz^{(m+1,m+1)}) . P(C_iz^{(m+1,m)}) ],
+//   k_xy = 1/(2 a_x^2 a_y^2), k_iz = 1/(4 a_i^2 a_z^2),
+// where C_iz^{(m,m')} is the (i, z) plaquette with its transverse links on slice m and
+// its longitudinal links on slice m'.  v is symmetric in the two slices, so with
+// f1(A, B) = -a_d dv(A, B)/dX (left variation U -> exp(iX) U of a slice-A link) the
+// force at time t is F = f1(U(t), U(t-dt)) + f1(U(t), U(t+dt)), and the step
+//   E(t+dt/2) = E(t-dt/2) + dt (F + j),  U(t+dt) = exp(i a dt E(t+dt/2)) U(t)
+// is solved by fixed-point iteration on E(t+dt/2); U(t-dt) = exp(-i a dt E(t-dt/2)) U(t).
+//
+// Derivative rule: for a term 2 Tr(P(C) Y) with C = F0 F1 F2 F3 based at b and
+// H = C Y + Y C^dag, a non-daggered factor k contributes +1/2 W^dag H W with W the
+// product of the factors before it, a daggered factor -1/2 W^dag H W with W the product
+// up to and including it, at the factor's own link.  For k = 3 (W = C) this is
+// -1/2 (Y C + C^dag Y); for the daggered k = 2 factor W = C F3.
+#include "internal.h"
+#include "stencil.h"
+
+namespace gl {
+
+// C_xy(b) = U_x(b) U_y(b+x) U_x^dag(b+y) U_y^dag(b) on one slice
+template <typename G, typename T>
+__device__ __forceinline__ typename G::Link loop_xy(const T* __restrict__ U, const Geom& g, Site b) {
+  using L = typename G::Link;
+  const int64_t Vp = g.Vp;
+  L a, bb, c, d;
+  load_link(a, U, 0, idx(g, b), Vp);
+  load_link(bb, U, 1, idx(g, shifted(g, b, 0, 1)), Vp);
+  load_link(c, U, 0, idx(g, shifted(g, b, 1, 1)), Vp);
+  load_link(d, U, 1, idx(g, b), Vp);
+  return G::mul_dag(G::mul_dag(G::mul(a, bb), c), d);
+}
+
+// C_iz(b) = U_i(b) U_z(b+i) U_i^dag(b+z) U_z^dag(b), transverse links from Ui, longitudinal from Uz
+template <typename G, typename T>
+__device__ __forceinline__ typename G::Link loop_iz(const T* __restrict__ Ui, const T* __restrict__ Uz,
+                                                    const Geom& g, Site b, int i) {
+  using L = typename G::Link;
+  const int64_t Vp = g.Vp;
+  L a, bb, c, d;
+  load_link(a, Ui, i, idx(g, b), Vp);
+  load_link(bb, Uz, 2, idx(g, shifted(g, b, i, 1)), Vp);
+  load_link(c, Ui, i, idx(g, shifted(g, b, 2, 1)), Vp);
+  load_link(d, Uz, 2, idx(g, b), Vp);
+  return G::mul_dag(G::mul_dag(G::mul(a, bb), c), d);
+}
+
+template <typename G>
+__device__ __forceinline__ typename G::Link herm_P(const typename G::Link& C) {
+  return G::herm_from_alg(G::proj(C));
+}
+// C Y + Y C^dag
+template <typename G>
+__device__ __forceinline__ typename G::Link Hf(const typename G::Link& C, const typename G::Link& Y) {
+  typename G::Link h = G::mul(C, Y);
+  G::add_to(h, G::mul_dag(Y, C), (typename G::Real)1);
+  return h;
+}
+// Y C + C^dag Y  (= C^dag H C)
+template <typename G>
+__device__ __forceinline__ typename G::Link Hb(const typename G::Link& C, const typename G::Link& Y) {
+  typename G::Link h = G::mul(Y, C);
+  G::add_to(h, G::dag_mul(C, Y), (typename G::Real)1);
+  return h;
+}
+// W^dag X W
+template <typename G>
+__device__ __forceinline__ typename G::Link conj_by(const typename G::Link& W, const typename G::Link& X) {
+  return G::dag_mul(W, G::mul(X, W));
+}
+
+// f1(A, B) for the link (y, d) of slice A: returns -a_d dv(A, B)/dX as components.
+template <typename G, typename T>
+__device__ typename G::Alg semi_f1(const T* __restrict__ A, const T* __restrict__ B, const Geom& g, Site y,
+                                   int d, const StepConst& c) {
+  using L = typename G::Link;
+  using R = typename G::Real;
+  const int64_t Vp = g.Vp;
+  L acc = G::zero();
+  if (d < 2) {
+    // (x, y) plane: loop C_xy[A] with Y = P(C_xy[B]) at the same base
+    const R kxy = (R)(0.5 / (c.a[0] * c.a[0] * c.a[1] * c.a[1]));
+    if (d == 0) {
+      {  // factor 0 at base y: +1/2 H
+        L C = loop_xy<G, T>(A, g, y), Y = herm_P<G>(loop_xy<G, T>(B, g, y));
+        G::add_to(acc, Hf<G>(C, Y), R(0.5) * kxy);
+      }
+      {  // factor 2 (daggered) at base y - y^: -1/2 F3^dag (Y C + C^dag Y) F3, F3 = U_y(b)
+        Site b = shifted(g, y, 1, -1);
+        L C = loop_xy<G, T>(A, g, b), Y = herm_P<G>(loop_xy<G, T>(B, g, b));
+        L F3;
+        load_link(F3, A, 1, idx(g, b), Vp);
+        G::add_to(acc, conj_by<G>(F3, Hb<G>(C, Y)), R(-0.5) * kxy);
+      }
+    } else {
+      {  // factor 1 at base y - x^: +1/2 F0^dag H F0, F0 = U_x(b)
+        Site b = shifted(g, y, 0, -1);
+        L C = loop_xy<G, T>(A, g, b), Y = herm_P<G>(loop_xy<G, T>(B, g, b));
+        L F0;
+        load_link(F0, A, 0, idx(g, b), Vp);
+        G::add_to(acc, conj_by<G>(F0, Hf<G>(C, Y)), R(0.5) * kxy);
+      }
+      {  // factor 3 (daggered) at base y: -1/2 (Y C + C^dag Y)
+        L C = loop_xy<G, T>(A, g, y), Y = herm_P<G>(loop_xy<G, T>(B, g, y));
+        G::add_to(acc, Hb<G>(C, Y), R(-0.5) * kxy);
+      }
+    }
+    // (d, z) plane: C_AA = C^{(A,A)}, C_AB = C^{(A,B)}; both carry this link as factors 0 and 2
+    const R kiz = (R)(0.25 / (c.a[d] * c.a[d] * c.a[2] * c.a[2]));
+    {  // base y, factor 0: +1/2 [H(C_AA, P_AB) + H(C_AB, P_AA)]
+      L Caa = loop_iz<G, T>(A, A, g, y, d), Cab = loop_iz<G, T>(A, B, g, y, d);
+      L Paa = herm_P<G>(Caa), Pab = herm_P<G>(Cab);
+      L h = Hf<G>(Caa, Pab);
+      G::add_to(h, Hf<G>(Cab, Paa), R(1));
+      G::add_to(acc, h, R(0.5) * kiz);
+    }
+    {  // base y - z^, factor 2 (daggered): -1/2 [F3a^dag Hb(C_AA, P_AB) F3a + F3b^dag Hb(C_AB, P_AA) F3b]
+      Site b = shifted(g, y, 2, -1);
+      L Caa = loop_iz<G, T>(A, A, g, b, d), Cab = loop_iz<G, T>(A, B, g, b, d);
+      L Paa = herm_P<G>(Caa), Pab = herm_P<G>(Cab);
+      L Fa, Fb;
+      load_link(Fa, A, 2, idx(g, b), Vp);
+      load_link(Fb, B, 2, idx(g, b), Vp);
+      L h = conj_by<G>(Fa, Hb<G>(Caa, Pab));
+      G::add_to(h, conj_by<G>(Fb, Hb<G>(Cab, Paa)), R(1));
+      G::add_to(acc, h, R(-0.5) * kiz);
+    }
+  } else {
+    // longitudinal link: planes (x, z) and (y, z); loops with z links on slice A:
+    // C_AA (Y = P(C_AB)) and C_BA (Y = P(C_BB)); the link is factor 1 at base y - i^
+    // and factor 3 (daggered) at base y
+#pragma unroll 1
+    for (int i = 0; i < 2; ++i) {
+      const R kiz = (R)(0.25 / (c.a[i] * c.a[i] * c.a[2] * c.a[2]));
+      {
+        Site b = shifted(g, y, i, -1);
+        L Caa = loop_iz<G, T>(A, A, g, b, i), Cab = loop_iz<G, T>(A, B, g, b, i);
+        L Cba = loop_iz<G, T>(B, A, g, b, i), Cbb = loop_iz<G, T>(B, B, g, b, i);
+        L Fa, Fb;
+        load_link(Fa, A, i, idx(g, b), Vp);
+        load_link(Fb, B, i, idx(g, b), Vp);
+        L h = conj_by<G>(Fa, Hf<G>(Caa, herm_P<G>(Cab)));
+        G::add_to(h, conj_by<G>(Fb, Hf<G>(Cba, herm_P<G>(Cbb))), R(1));
+        G::add_to(acc, h, R(0.5) * kiz);
+      }
+      {
+        L Caa = loop_iz<G, T>(A, A, g, y, i), Cab = loop_iz<G, T>(A, B, g, y, i);
+        L Cba = loop_iz<G, T>(B, A, g, y, i), Cbb = loop_iz<G, T>(B, B, g, y, i);
+        L h = Hb<G>(Caa, herm_P<G>(Cab));
+        G::add_to(h, Hb<G>(Cba, herm_P<G>(Cbb)), R(1));
+        G::add_to(acc, h, R(-0.5) * kiz);
+      }
+    }
+  }
+  typename G::Alg f = G::alg_from_herm(acc);
+  const R ka = (R)(-c.a[d]);
+#pragma unroll
+  for (int k = 0; k < G::NG; ++k) f.c[k] *= ka;
+  return f;
+}
+
+template <typename G>
+__device__ __forceinline__ void site_of(const Geom& g, uint32_t s, Site& x) {
+  x.x = (int)(s % (uint32_t)g.nt);
+  x.y = (int)((s / (uint32_t)g.nt) % (uint32_t)g.nt);
+  x.z = (int)(s / (uint32_t)g.layer);
+}
+
+// out = f1(Uc, Uo) for every link (direction = blockIdx.y)
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_semi_f1(const T* __restrict__ Uc, const T* __restrict__ Uo,
+                                                 T* __restrict__ out, Geom g, StepConst c) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  Site x;
+  site_of<G>(g, s, x);
+  const int d = blockIdx.y;
+  typename G::Alg f = semi_f1<G, T>(Uc, Uo, g, x, d, c);
+  store_alg(f, out, d, s, g.Vp);
+}
+
+// U(t-dt) = exp(-i a dt E) U(t) into Up, first trial U(t+dt) = exp(+i a dt E) U(t) into Ut,
+// first trial E(t+dt/2) = E(t-dt/2) into Et
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_semi_begin(const T* __restrict__ U, const T* __restrict__ E,
+                                                    T* __restrict__ Up, T* __restrict__ Ut, T* __restrict__ Et,
+                                                    Geom g, StepConst c) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  const int d = blockIdx.y;
+  typename G::Link u;
+  typename G::Alg e;
+  load_link(u, U, d, s, g.Vp);
+  load_alg(e, E, d, s, g.Vp);
+  const typename G::Real k = (typename G::Real)(c.a[d] * c.dt);
+  store_link(G::mul(G::expi(e, -k), u), Up, d, s, g.Vp);
+  store_link(G::mul(G::expi(e, k), u), Ut, d, s, g.Vp);
+  store_alg(e, Et, d, s, g.Vp);
+}
+
+// hop of both charge populations with the links U(t) and the current dt j_z = a_L (rho_A' - rho_B)
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_semi_hop(const T* __restrict__ U, T* __restrict__ rhoA,
+                                                  T* __restrict__ rhoB, T* __restrict__ J, Geom g, StepConst c) {
+  using A = typename G::Alg;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  Site x;
+  site_of<G>(g, s, x);
+  const int64_t Vp = g.Vp;
+  typename G::Link Uz;
+  load_link(Uz, U, 2, s, Vp);
+  const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
+  const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
+  A rb, ra;
+  load_alg(rb, rhoB, 0, sB, Vp);
+  load_alg(ra, rhoA, 0, sA, Vp);
+  A rbn = G::transport(Uz, rb);
+  A ran = G::transport_inv(Uz, ra);
+  store_alg(rbn, rhoB, 0, sB, Vp);
+  store_alg(ran, rhoA, 0, sA, Vp);
+  A jz;
+  const typename G::Real al = (typename G::Real)c.a[2];
+#pragma unroll
+  for (int k = 0; k < G::NG; ++k) jz.c[k] = al * (ran.c[k] - rb.c[k]);
+  store_alg(jz, J, 0, s, Vp);
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
+}
+
+// One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
+// Et <- E'; conv[0] = max |E' - Et_old|, conv[1] = max |E'| (component-wise).
+template <typename G, typename T, bool HOP>
+__global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
+                                                   const T* __restrict__ E, const T* __restrict__ F2,
+                                                   const T* __restrict__ J, T* __restrict__ Et,
+                                                   T* __restrict__ Ut_out, double* __restrict__ conv, Geom g,
+                                                   StepConst c) {
+  using A = typename G::Alg;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  double dmax = 0.0, emax = 0.0;
+  if (s < (uint32_t)g.V) {
+    Site x;
+    site_of<G>(g, s, x);
+    const int d = blockIdx.y;
+    const int64_t Vp = g.Vp;
+    A f = semi_f1<G, T>(Uc, Ut_in, g, x, d, c);
+    A e, f2, eo;
+    load_alg(e, E, d, s, Vp);
+    load_alg(f2, F2, d, s, Vp);
+    load_alg(eo, Et, d, s, Vp);
+    const typename G::Real dt = (typename G::Real)c.dt;
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) e.c[k] += dt * (f.c[k] + f2.c[k]);
+    if (HOP && d == 2) {
+      A j;
+      load_alg(j, J, 0, s, Vp);
+#pragma unroll
+      for (int k = 0; k < G::NG; ++k) e.c[k] += j.c[k];
+    }
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) {
+      dmax = fmax(dmax, fabs((double)e.c[k] - (double)eo.c[k]));
+      emax = fmax(emax, fabs((double)e.c[k]));
+    }
+    store_alg(e, Et, d, s, Vp);
+    typename G::Link u;
+    load_link(u, Uc, d, s, Vp);
+    store_link(G::mul(G::expi(e, (typename G::Real)(c.a[d] * c.dt)), u), Ut_out, d, s, Vp);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmax = fmax(dmax, __shfl_down(dmax, o, 64));
+    emax = fmax(emax, __shfl_down(emax, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(conv, dmax);
+    atomic_max_nonneg(conv + 1, emax);
+  }
+}
+
+template <typename G, typename T>
+__global__ void k_copy_alg(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[k];
+}
+
+template <typename G, typename T>
+void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_semi_f1<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, Uc, Uo, out, g, c);
+}
+
+template <typename G, typename T>
+void launch_semi_begin(const T* U, const T* E, T* Up, T* Ut, T* Et, const Geom& g, const StepConst& c,
+                       hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_semi_begin<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, U, E, Up, Ut, Et,
+                     g, c);
+}
+
+template <typename G, typename T>
+void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, const Geom& g, const StepConst& c, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_semi_hop<G, T>), dim3((unsigned)((g.V + bs - 1) / bs)), dim3(bs), 0, st, U, rhoA, rhoB, J, g, c);
+}
+
+template <typename G, typename T>
+void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
+                      double* conv, const Geom& g, const StepConst& c, hipStream_t st) {
+  const int bs = 256;
+  dim3 grid((unsigned)((g.V + bs - 1) / bs), 3);
+  if (c.hop)
+    hipLaunchKernelGGL((k_semi_iter<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+  else
+    hipLaunchKernelGGL((k_semi_iter<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+}
+
+template <typename G, typename T>
+void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_copy_alg<G, T>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, src, dst, n);
+}
+
+#define GL_SEMI_INST(G, T)                                                                                      \
+  template void launch_semi_f1<G, T>(const T*, const T*, T*, const Geom&, const StepConst&, hipStream_t);      \
+  template void launch_semi_begin<G, T>(const T*, const T*, T*, T*, T*, const Geom&, const StepConst&,         \
+                                        hipStream_t);                                                          \
+  template void launch_semi_hop<G, T>(const T*, T*, T*, T*, const Geom&, const StepConst&, hipStream_t);       \
+  template void launch_semi_iter<G, T>(const T*, const T*, const T*, const T*, const T*, T*, T*, double*,      \
+                                       const Geom&, const StepConst&, hipStream_t);                            \
+  template void launch_copy<G, T>(const T*, T*, int64_t, hipStream_t);
+GL_SEMI_INST(Su2<double>, double)
+GL_SEMI_INST(Su3<double>, double)
+GL_SEMI_INST(Su2<float>, float)
+GL_SEMI_INST(Su3<float>, float)
+
+}  // namespace gl

@@ -63,6 +63,13 @@ class Lattice:
         self._chk(lib.glasma_reunitarize(self.ctx))
 
     @property
+    def last_iterations(self):
+        """Fixed-point iterations of the last semi-implicit step."""
+        n = C.c_int32()
+        self._chk(lib.glasma_last_iterations(self.ctx, C.byref(n)))
+        return n.value
+
+    @property
     def step_count(self):
         s = C.c_int64()
         self._chk(lib.glasma_get_step(self.ctx, C.byref(s)))

@@ -1,0 +1,58 @@
+"""GPU parity of the semi-implicit scheme against the oracle: per field component over
+several steps with CPIC hops, the initial charges of the modified Gauss law, and its
+conservation on the GPU states (evaluated by the oracle)."""
+import sys
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice, init_mv, observables, semi_implicit as si
+from _gpu import gpu, lattice_or_skip, to_comp, from_comp, state_errs, mv_setup, new_lattice
+
+pytestmark = gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("nc,nz,nt,dt", [(2, 16, 4, 1.0), (3, 24, 6, 0.5), (3, 16, 5, 1.0)])
+def test_semi_implicit_parity(nc, nz, nt, dt):
+    pkg = lattice_or_skip()
+    w = synth.Workload(f"su{nc}-{nz}x{nt}", nc=nc, nz=nz, nt=nt, dt=dt, mu=0.5, sigma=1.5, seed=300 + nz)
+    say("case: semi-implicit", w.name, "dt", dt)
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, nc, nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, nz, p, mv)
+    st = si.charges_for_scheme(st)
+    lat = new_lattice(pkg, w, scheme=1, max_iter=100, tol=1e-15)
+    lat.init_state(*to_comp(st), step0=0)
+    for s in range(5):
+        st = si.semi_implicit_step(st, tol=1e-15)
+        lat.step(1)
+        errs = state_errs(lat.get_state(), st)
+        say(" step", s + 1, "iters", lat.last_iterations, {k: f"{v:.1e}" for k, v in errs.items()})
+        assert max(errs.values()) < 1e-10, (s, errs)
+    gst = from_comp(lat.get_state(), nc, (nz, nt, nt), p)
+    assert si.gauss_mod_residual(gst) < 1e-12
+    go = lat.observables()
+    oo = observables.observables(st, E_new=st.E)
+    sl = oo["tmunu_z"]
+    assert np.max(np.abs(go["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True)) < 1e-9
+
+
+def test_semi_implicit_init_mv_charges():
+    pkg = lattice_or_skip()
+    w = synth.Workload("su3-32x6", nc=3, nz=32, nt=6, dt=1.0, mu=0.5, sigma=2.0, seed=330)
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    st = si.charges_for_scheme(st)
+    lat = new_lattice(pkg, w, scheme=1, max_iter=100, tol=1e-14)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    errs = state_errs(lat.get_state(), st)
+    assert max(errs.values()) < 1e-10, errs
+    lat.step(8)
+    gst = from_comp(lat.get_state(), 3, (w.nz, w.nt, w.nt), p)
+    assert si.gauss_mod_residual(gst) < 1e-12
