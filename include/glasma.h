@@ -167,6 +167,44 @@ int glasma_last_iterations(const glasma_ctx* ctx, int32_t* iters);
 /* Current step counter (host value). */
 int glasma_get_step(const glasma_ctx* ctx, int64_t* step);
 
+/* ---- Batched form ---------------------------------------------------------
+ * Many independent events (one MV collision each) of different lattice sizes share
+ * one pool of device memory and advance together: one launch per step covers every
+ * event (workgroups loop over (event, block of sites) items), and glasma_batch_run
+ * replays a captured HIP graph of `graph_chunk` steps.  The leapfrog scheme only;
+ * reunitarisation (reunit_every) is fused into the step.  Each event is a regular
+ * context (glasma_batch_event) for initial conditions, observables and state I/O,
+ * all events must be at the same step when the batch runs. */
+typedef struct glasma_batch glasma_batch;
+
+/* Pool bytes for n_events events of sizes nz[e] x nt[e] x nt[e] with the common
+ * parameters (its nz, nt are ignored; scheme must be 0). */
+int glasma_batch_layout(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
+                        size_t* pool_bytes);
+
+/* Create the batch over a caller-owned device pool of glasma_batch_layout bytes. */
+int glasma_batch_create(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
+                        void* pool, void* stream, glasma_batch** out);
+
+int glasma_batch_destroy(glasma_batch* b);
+const char* glasma_batch_last_error(const glasma_batch* b);
+
+/* The context of event e (owned by the batch: do not destroy it). */
+int glasma_batch_event(glasma_batch* b, int32_t e, glasma_ctx** ctx);
+
+/* Advance every event by `steps` steps; graph_chunk > 0 captures that many steps in a
+ * HIP graph (kept for later calls with the same chunk and tiling) and replays it. */
+int glasma_batch_run(glasma_batch* b, int32_t steps, int32_t graph_chunk);
+
+/* Work-item tiling: sites per item (64, 128 or 256 threads per workgroup) and the
+ * number of persistent workgroups (0: one workgroup per item). */
+int glasma_batch_set_tiling(glasma_batch* b, int32_t sites_per_item, int32_t grid);
+
+/* Autotuner: times every tiling candidate over `steps` steps (HIP events) and keeps the
+ * fastest; writes a JSON report (may be NULL).  Advances the state by 13 * steps steps,
+ * so call it before setting up the events that are to be measured. */
+int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t report_len);
+
 /* Host-side evaluation of the library's group kernels, for CPU tests of the
  * device algebra (the same inline functions the GPU kernels use).  op:
  *   0: out = exp(i s X) as a link      in = [s, X^a]                (n_g + 1 in)

@@ -64,6 +64,14 @@ def _load():
         "glasma_get_step": ([P, C.POINTER(I64)], C.c_int),
         "glasma_last_iterations": ([P, C.POINTER(I32)], C.c_int),
         "glasma_host_group_op": ([I32, I32, I32, I64, D, D], C.c_int),
+        "glasma_batch_layout": ([C.POINTER(Params), I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(C.c_size_t)], C.c_int),
+        "glasma_batch_create": ([C.POINTER(Params), I32, C.POINTER(I32), C.POINTER(I32), V, V, C.POINTER(P)], C.c_int),
+        "glasma_batch_destroy": ([P], C.c_int),
+        "glasma_batch_last_error": ([P], C.c_char_p),
+        "glasma_batch_event": ([P, I32, C.POINTER(P)], C.c_int),
+        "glasma_batch_run": ([P, I32, I32], C.c_int),
+        "glasma_batch_set_tiling": ([P, I32, I32], C.c_int),
+        "glasma_batch_autotune": ([P, I32, C.c_char_p, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -78,6 +86,13 @@ lib = _load()
 def check(rc, ctx=None):
     if rc != GLASMA_OK:
         msg = lib.glasma_last_error(ctx)
+        raise GlasmaError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check_batch(rc, b=None):
+    if rc != GLASMA_OK:
+        msg = lib.glasma_batch_last_error(b)
         raise GlasmaError(rc, msg.decode() if msg else "")
     return rc
 

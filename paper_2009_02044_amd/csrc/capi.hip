@@ -489,3 +489,301 @@ int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const do
   return GLASMA_OK;
 }
 
+
+// ============================================================================
+// Batched form: many events of different lattice sizes advanced together by one
+// launch per step (workgroups loop over (event, block) work items), replayed from a
+// captured HIP graph.  Each event is a full context over its own slice of the pool.
+// ============================================================================
+struct glasma_batch {
+  glasma_params p;                 // common parameters (nz, nt unused)
+  std::vector<glasma_ctx*> ev;
+  std::vector<size_t> ev_off;      // byte offset of each event's buffers in the pool
+  char* pool;
+  hipStream_t stream;
+  EventDesc* d_ev;                 // device event table
+  uint32_t* d_item_event;          // device item -> event map
+  int64_t* d_ctr;                  // device step counter
+  uint32_t items_for_bs[257];      // item count for each sites-per-item value (cached lazily)
+  int bs, grid;                    // chosen sites per item and persistent grid (0 = one per item)
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int graph_steps, graph_bs, graph_grid;
+  std::string err;
+  std::string tune_report;
+};
+
+static int bfail(glasma_batch* b, int code, const std::string& m) {
+  if (b) b->err = m; else g_err = m;
+  return code;
+}
+
+#define BHIPCHK(b, call)                                                                                  \
+  do {                                                                                                    \
+    hipError_t e_ = (call);                                                                               \
+    if (e_ != hipSuccess) return bfail(b, GLASMA_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static glasma_params event_params(const glasma_params* common, int32_t nz, int32_t nt) {
+  glasma_params q = *common;
+  q.nz = nz;
+  q.nt = nt;
+  q.scheme = 0;
+  return q;
+}
+
+// pool layout: per event [U | U_alt | E | rhoA | rhoB | work], then the event table,
+// the item map for the smallest work item (64 sites) and the step counter
+static int batch_sizes(const glasma_params* common, int32_t n, const int32_t* nz, const int32_t* nt,
+                       std::vector<size_t>* offs, size_t* table_off, size_t* items_off, size_t* ctr_off,
+                       size_t* total) {
+  if (!common || n < 1 || !nz || !nt) return fail(nullptr, GLASMA_E_ARG, "bad batch arguments");
+  if (common->scheme != 0) return fail(nullptr, GLASMA_E_ARG, "the batched form runs the leapfrog scheme");
+  size_t off = 0;
+  uint64_t items64 = 0;
+  for (int32_t e = 0; e < n; ++e) {
+    glasma_params q = event_params(common, nz[e], nt[e]);
+    size_t b[6];
+    int rc = glasma_layout(&q, b);
+    if (rc) return rc;
+    if (offs) offs->push_back(off);
+    for (int k = 0; k < 6; ++k) off += align256(b[k]);
+    items64 += (uint64_t)(geom_of(&q).V + 63) / 64;
+  }
+  *table_off = off;
+  off += align256((size_t)n * sizeof(EventDesc));
+  *items_off = off;
+  off += align256((size_t)items64 * sizeof(uint32_t));
+  *ctr_off = off;
+  off += 256;
+  *total = off;
+  return GLASMA_OK;
+}
+
+int glasma_batch_layout(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
+                        size_t* pool_bytes) {
+  size_t t, i, c, tot;
+  int rc = batch_sizes(common, n_events, nz, nt, nullptr, &t, &i, &c, &tot);
+  if (rc) return rc;
+  if (!pool_bytes) return fail(nullptr, GLASMA_E_ARG, "pool_bytes is NULL");
+  *pool_bytes = tot;
+  return GLASMA_OK;
+}
+
+int glasma_batch_create(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
+                        void* pool, void* stream, glasma_batch** out) {
+  std::vector<size_t> offs;
+  size_t toff, ioff, coff, tot;
+  int rc = batch_sizes(common, n_events, nz, nt, &offs, &toff, &ioff, &coff, &tot);
+  if (rc) return rc;
+  if (!pool || !out) return fail(nullptr, GLASMA_E_ARG, "pool or out is NULL");
+  glasma_batch* b = new glasma_batch();
+  b->p = *common;
+  b->pool = (char*)pool;
+  b->stream = (hipStream_t)stream;
+  b->ev_off = offs;
+  for (int32_t e = 0; e < n_events; ++e) {
+    glasma_params q = event_params(common, nz[e], nt[e]);
+    size_t sz[6];
+    glasma_layout(&q, sz);
+    char* base = b->pool + offs[e];
+    glasma_buffers bf;
+    void** slots[6] = {&bf.U, &bf.U_alt, &bf.E, &bf.rhoA, &bf.rhoB, &bf.work};
+    size_t o = 0;
+    for (int k = 0; k < 6; ++k) { *slots[k] = base + o; o += align256(sz[k]); }
+    glasma_ctx* c = nullptr;
+    rc = glasma_create(&q, &bf, stream, &c);
+    if (rc) {
+      for (auto* x : b->ev) glasma_destroy(x);
+      delete b;
+      return rc;
+    }
+    b->ev.push_back(c);
+  }
+  b->d_ev = (EventDesc*)(b->pool + toff);
+  b->d_item_event = (uint32_t*)(b->pool + ioff);
+  b->d_ctr = (int64_t*)(b->pool + coff);
+  b->bs = 256;
+  b->grid = 0;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->graph_steps = b->graph_bs = b->graph_grid = 0;
+  *out = b;
+  return GLASMA_OK;
+}
+
+int glasma_batch_destroy(glasma_batch* b) {
+  if (!b) return GLASMA_OK;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (auto* c : b->ev) glasma_destroy(c);
+  delete b;
+  return GLASMA_OK;
+}
+
+const char* glasma_batch_last_error(const glasma_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+static int batch_event(glasma_batch* b, int32_t e, glasma_ctx** c) {
+  if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
+  if (e < 0 || e >= (int32_t)b->ev.size()) return bfail(b, GLASMA_E_ARG, "event index out of range");
+  *c = b->ev[e];
+  return GLASMA_OK;
+}
+
+int glasma_batch_event(glasma_batch* b, int32_t e, glasma_ctx** ctx) { return batch_event(b, e, ctx); }
+
+// Event table and item map for `bs` sites per item; every event must be at the same step.
+static int batch_prepare(glasma_batch* b, int bs, BatchConst* bc) {
+  const int64_t s0 = b->ev[0]->step;
+  std::vector<EventDesc> tab(b->ev.size());
+  std::vector<uint32_t> items;
+  for (size_t e = 0; e < b->ev.size(); ++e) {
+    glasma_ctx* c = b->ev[e];
+    if (!c->ready) return bfail(b, GLASMA_E_STATE, "an event has no state");
+    if (c->step != s0) return bfail(b, GLASMA_E_STATE, "events are at different steps");
+    EventDesc& d = tab[e];
+    d.g = c->g;
+    // the buffer current now is current at steps of this parity
+    const bool even_now = (s0 & 1) == 0;
+    void* cur = c->cur ? c->b.U_alt : c->b.U;
+    void* oth = c->cur ? c->b.U : c->b.U_alt;
+    d.Ueven = even_now ? cur : oth;
+    d.Uodd = even_now ? oth : cur;
+    d.E = c->b.E;
+    d.rhoA = c->b.rhoA;
+    d.rhoB = c->b.rhoB;
+    d.item0 = (uint32_t)items.size();
+    d.off0 = c->offA;
+    d.hops0 = hop_count(c, s0 - 1);
+    const uint32_t n = (uint32_t)((c->g.V + bs - 1) / bs);
+    for (uint32_t k = 0; k < n; ++k) items.push_back((uint32_t)e);
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->d_ev, tab.data(), tab.size() * sizeof(EventDesc), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->d_item_event, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                            b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->d_ctr, &s0, sizeof(int64_t), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  glasma_ctx* c0 = b->ev[0];
+  bc->a[0] = b->p.a_T; bc->a[1] = b->p.a_T; bc->a[2] = b->p.a_L;
+  bc->dt = b->p.dt;
+  bc->hop_p = c0->hop_p;
+  bc->hop_q = c0->hop_q;
+  bc->reunit_every = b->p.reunit_every;
+  bc->items = (uint32_t)items.size();
+  return GLASMA_OK;
+}
+
+static void batch_launch_one(glasma_batch* b, const BatchConst& bc, int bs, int grid) {
+  const int g = grid > 0 ? grid : (int)bc.items;
+  glasma_ctx* c0 = b->ev[0];
+  dispatch(c0, [&]<typename G, typename T>() -> int {
+    launch_batch_step<G, T>(b->d_ev, b->d_item_event, bc, b->d_ctr, g, bs, b->stream);
+    return 0;
+  });
+  launch_batch_tick(b->d_ctr, b->stream);
+}
+
+// host bookkeeping of every event after n steps
+static void batch_advance(glasma_batch* b, int32_t n) {
+  for (auto* c : b->ev) {
+    const int64_t h = hop_count(c, c->step + n - 1) - hop_count(c, c->step - 1);
+    c->offA = (int)((c->offA + h) % c->g.nz);
+    c->offB = (int)((c->offB + h) % c->g.nz);
+    c->cur = (c->cur + n) & 1;
+    c->step += n;
+  }
+}
+
+int glasma_batch_run(glasma_batch* b, int32_t steps, int32_t graph_chunk) {
+  if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
+  if (steps < 0 || graph_chunk < 0) return bfail(b, GLASMA_E_ARG, "steps and graph_chunk must be >= 0");
+  if (steps == 0) return GLASMA_OK;
+  BatchConst bc;
+  int rc = batch_prepare(b, b->bs, &bc);
+  if (rc) return rc;
+  int32_t done = 0;
+  if (graph_chunk > 0 && steps >= graph_chunk) {
+    if (!b->exec || b->graph_steps != graph_chunk || b->graph_bs != b->bs || b->graph_grid != b->grid) {
+      if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+      BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int32_t k = 0; k < graph_chunk; ++k) batch_launch_one(b, bc, b->bs, b->grid);
+      BHIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
+      BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_steps = graph_chunk;
+      b->graph_bs = b->bs;
+      b->graph_grid = b->grid;
+    }
+    // the captured launches carry the item count of this event set and tile size
+    while (steps - done >= graph_chunk) {
+      BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+      done += graph_chunk;
+    }
+  }
+  for (; done < steps; ++done) batch_launch_one(b, bc, b->bs, b->grid);
+  BHIPCHK(b, hipGetLastError());
+  batch_advance(b, steps);
+  return GLASMA_OK;
+}
+
+int glasma_batch_set_tiling(glasma_batch* b, int32_t sites_per_item, int32_t grid) {
+  if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
+  if (sites_per_item != 64 && sites_per_item != 128 && sites_per_item != 256)
+    return bfail(b, GLASMA_E_ARG, "sites_per_item must be 64, 128 or 256");
+  if (grid < 0) return bfail(b, GLASMA_E_ARG, "grid must be >= 0");
+  b->bs = sites_per_item;
+  b->grid = grid;
+  return GLASMA_OK;
+}
+
+// Time every (sites per item, grid) candidate over `steps` steps with HIP events and
+// keep the fastest; the state advances by (candidates + 1) * steps steps.
+int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t report_len) {
+  if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
+  if (steps < 1) return bfail(b, GLASMA_E_ARG, "steps must be >= 1");
+  const int bss[3] = {64, 128, 256};
+  const int grids[4] = {0, 4096, 2048, 1024};
+  hipEvent_t e0, e1;
+  BHIPCHK(b, hipEventCreate(&e0));
+  BHIPCHK(b, hipEventCreate(&e1));
+  std::string rep = "{\"candidates\": [";
+  float best = 1e30f;
+  int bb = 256, bg = 0;
+  bool first = true;
+  // warm-up with the current tiling
+  int rc = glasma_batch_run(b, steps, 0);
+  if (rc) return rc;
+  for (int bs : bss)
+    for (int gr : grids) {
+      b->bs = bs;
+      b->grid = gr;
+      BHIPCHK(b, hipEventRecord(e0, b->stream));
+      rc = glasma_batch_run(b, steps, 0);
+      if (rc) return rc;
+      BHIPCHK(b, hipEventRecord(e1, b->stream));
+      BHIPCHK(b, hipEventSynchronize(e1));
+      float ms = 0.f;
+      BHIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)steps;
+      char buf[128];
+      snprintf(buf, sizeof(buf), "%s{\"sites_per_item\": %d, \"grid\": %d, \"ms_per_step\": %.4f}", first ? "" : ", ",
+               bs, gr, ms);
+      rep += buf;
+      first = false;
+      if (ms < best) { best = ms; bb = bs; bg = gr; }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->bs = bb;
+  b->grid = bg;
+  char buf[160];
+  snprintf(buf, sizeof(buf), "], \"chosen\": {\"sites_per_item\": %d, \"grid\": %d, \"ms_per_step\": %.4f}}", bb, bg,
+           best);
+  rep += buf;
+  b->tune_report = rep;
+  if (report && report_len > 0) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return GLASMA_OK;
+}

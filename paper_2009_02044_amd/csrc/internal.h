@@ -10,6 +10,30 @@ template <typename G, typename T>
 void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
                      hipStream_t st);
 
+// Batched form (step.hip): one descriptor per event, workgroups loop over work items.
+struct EventDesc {
+  Geom g;
+  const void* Ueven;  // link buffer that is current at even steps
+  const void* Uodd;   // link buffer that is current at odd steps
+  void* E;
+  void* rhoA;
+  void* rhoB;
+  uint32_t item0;     // first work item of the event
+  int32_t off0;       // charge offset at the reference step
+  int64_t hops0;      // hop count S(s_ref - 1) at the reference step
+};
+struct BatchConst {
+  double a[3];
+  double dt;
+  int64_t hop_p, hop_q;  // dt / a_L = hop_p / hop_q
+  int reunit_every;
+  uint32_t items;
+};
+template <typename G, typename T>
+void launch_batch_step(const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc, const int64_t* ctr,
+                       int grid, int bs, hipStream_t st);
+void launch_batch_tick(int64_t* ctr, hipStream_t st);
+
 // Observables at the current integer time, written to `out` (device, double):
 // [0, 4 nz): transverse means eps, p_L, p_T, S_L per layer; then OBS_* scalars.
 enum {

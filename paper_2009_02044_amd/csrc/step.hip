@@ -23,7 +23,8 @@ namespace gl {
 template <typename G, typename T, bool HOP>
 __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restrict__ Unew, T* __restrict__ E,
                                             T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
-                                            const StepConst& c, const double* inv_a2, Site x, uint32_t s, int i) {
+                                            const StepConst& c, const double* inv_a2, Site x, uint32_t s, int i,
+                                            bool reunit = false) {
   using L = typename G::Link;
   using A = typename G::Alg;
   constexpr int NG = G::NG;
@@ -54,7 +55,17 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
   }
   store_alg(e, E, i, s, Vp);
   L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
-  store_link(Un, Unew, i, s, Vp);
+  if (reunit) {
+    // projection back onto SU(N) in double arithmetic
+    using Gd = typename GroupOf<G::NC, double>::type;
+    typename Gd::Link ud;
+    const T* un = reinterpret_cast<const T*>(&Un);
+    double* dd = reinterpret_cast<double*>(&ud);
+    for (int k = 0; k < (int)(sizeof(L) / sizeof(T)); ++k) dd[k] = (double)un[k];
+    store_link(Gd::reunit(ud), Unew, i, s, Vp);
+  } else {
+    store_link(Un, Unew, i, s, Vp);
+  }
 }
 
 // Update of link (x, i) from its staple sum S (the z-link thread also hops the charges).
@@ -177,6 +188,71 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
       hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
   }
 }
+
+// ---- batched form: many events of different sizes in one launch --------------
+// Work item = `bs` consecutive sites of one event; workgroups loop over the items
+// (persistent when the grid is smaller than the item count).  The step number comes
+// from device memory so that a captured graph of several steps replays correctly:
+// parity of the link buffers, hop flag and charge offsets all follow from it.
+GL_HD int64_t hop_count_dev(int64_t s, int64_t p, int64_t q) { return ((2 * s + 1) * p + q) / (2 * q); }
+
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_batch_step(const EventDesc* __restrict__ ev,
+                                                    const uint32_t* __restrict__ item_event, BatchConst bc,
+                                                    const int64_t* __restrict__ ctr) {
+  const int64_t st = ctr[0];
+  const int64_t S1 = hop_count_dev(st, bc.hop_p, bc.hop_q), S0 = hop_count_dev(st - 1, bc.hop_p, bc.hop_q);
+  const bool hop = S1 > S0;
+  const bool reunit = bc.reunit_every > 0 && ((st + 1) % bc.reunit_every) == 0;
+  const double inv_a2[3] = {1.0 / (bc.a[0] * bc.a[0]), 1.0 / (bc.a[1] * bc.a[1]), 1.0 / (bc.a[2] * bc.a[2])};
+  for (uint32_t item = blockIdx.x; item < bc.items; item += gridDim.x) {
+    const EventDesc d = ev[item_event[item]];
+    const uint32_t s = (item - d.item0) * blockDim.x + threadIdx.x;
+    if (s >= (uint32_t)d.g.V) continue;
+    StepConst c;
+    c.a[0] = bc.a[0]; c.a[1] = bc.a[1]; c.a[2] = bc.a[2];
+    c.dt = bc.dt;
+    c.hop = hop ? 1 : 0;
+    const int64_t off = (d.off0 + (S0 - d.hops0)) % d.g.nz;
+    c.offA = (int)off;
+    c.offB = (int)off;
+    c.scheme = 0;
+    const bool odd = (st & 1) != 0;
+    const T* U = (const T*)(odd ? d.Uodd : d.Ueven);
+    T* Un = (T*)(odd ? d.Ueven : d.Uodd);
+    Site x;
+    x.x = (int)(s % (uint32_t)d.g.nt);
+    x.y = (int)((s / (uint32_t)d.g.nt) % (uint32_t)d.g.nt);
+    x.z = (int)(s / (uint32_t)d.g.layer);
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      if (hop)
+        update_link<G, T, true>(U, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
+      else
+        update_link<G, T, false>(U, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
+    }
+  }
+}
+
+// advance the device step counter (one lane writes)
+__global__ void k_batch_tick(int64_t* ctr) {
+  if (threadIdx.x == 0) {
+    const int64_t v = ctr[0];
+    ctr[threadIdx.x] = v + 1;
+  }
+}
+
+template <typename G, typename T>
+void launch_batch_step(const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc, const int64_t* ctr,
+                       int grid, int bs, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch_step<G, T>), dim3((unsigned)grid), dim3((unsigned)bs), 0, st, ev, item_event, bc, ctr);
+}
+void launch_batch_tick(int64_t* ctr, hipStream_t st) { hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, st, ctr); }
+
+template void launch_batch_step<Su2<double>, double>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su3<double>, double>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su2<float>, float>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su3<float>, float>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
 
 template void launch_leapfrog<Su2<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);
 template void launch_leapfrog<Su3<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);

@@ -13,7 +13,15 @@ class Lattice:
     nz x nt x nt lattice held in caller-owned (torch) device buffers."""
 
     def __init__(self, nc, nz, nt, a_T=4.0, a_L=1.0, dt=0.5, fp=64, scheme=0,
-                 reunit_every=0, max_iter=50, tol=0.0, device="cuda"):
+                 reunit_every=0, max_iter=50, tol=0.0, device="cuda", _ctx=None, _stream=None):
+        if _ctx is not None:      # a view of an event owned by a Batch
+            self.params = _lib.Params(nc, nz, nt, a_T, a_L, dt, fp, scheme, reunit_every, max_iter, tol)
+            self.device = torch.device(device)
+            self.stream = _stream
+            self.ctx = _ctx
+            self._owned = False
+            self._set_dims(nc, nz, nt, fp)
+            return
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP library needs a GPU; no device is visible")
         self.params = _lib.Params(nc, nz, nt, a_T, a_L, dt, fp, scheme, reunit_every, max_iter, tol)
@@ -27,6 +35,10 @@ class Lattice:
         self.ctx = C.c_void_p()
         check(lib.glasma_create(C.byref(self.params), C.byref(b), C.c_void_p(self.stream.cuda_stream),
                                 C.byref(self.ctx)))
+        self._owned = True
+        self._set_dims(nc, nz, nt, fp)
+
+    def _set_dims(self, nc, nz, nt, fp):
         self.nc, self.nz, self.nt, self.fp = nc, nz, nt, fp
         self.ng = nc * nc - 1
         self.r = 4 if nc == 2 else 18
@@ -35,7 +47,7 @@ class Lattice:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx is not None and ctx.value:
+        if getattr(self, "_owned", False) and ctx is not None and ctx.value:
             lib.glasma_destroy(ctx)
             self.ctx = None
 
@@ -111,6 +123,56 @@ class Lattice:
         out = {k: float(s[v]) for k, v in _lib.OBS.items()}
         out["tmunu_z"] = h[:4 * nz].reshape(4, nz)
         return out
+
+
+class Batch:
+    """Many events of different sizes in one device pool, advanced together
+    (glasma_batch_*).  The batch runs on its own (non-default) stream so that steps can
+    be captured in a HIP graph; every event is reachable as a Lattice view."""
+
+    def __init__(self, nc, shapes, a_T=4.0, a_L=1.0, dt=0.5, fp=32, reunit_every=8, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU; no device is visible")
+        from ._lib import check_batch
+        self._check = check_batch
+        self.params = _lib.Params(nc, 0, 0, a_T, a_L, dt, fp, 0, reunit_every, 1, 0.0)
+        n = len(shapes)
+        self.nz = (C.c_int32 * n)(*[int(s[0]) for s in shapes])
+        self.nt = (C.c_int32 * n)(*[int(s[1]) for s in shapes])
+        size = C.c_size_t()
+        check_batch(lib.glasma_batch_layout(C.byref(self.params), n, self.nz, self.nt, C.byref(size)))
+        self.device = torch.device(device)
+        self.pool = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.b = C.c_void_p()
+        check_batch(lib.glasma_batch_create(C.byref(self.params), n, self.nz, self.nt,
+                                            C.c_void_p(self.pool.data_ptr()),
+                                            C.c_void_p(self.stream.cuda_stream), C.byref(self.b)))
+        self.events = []
+        for e in range(n):
+            ctx = C.c_void_p()
+            check_batch(lib.glasma_batch_event(self.b, e, C.byref(ctx)), self.b)
+            self.events.append(Lattice(nc, shapes[e][0], shapes[e][1], a_T, a_L, dt, fp, 0, reunit_every,
+                                       1, 0.0, device, _ctx=ctx, _stream=self.stream))
+        self.sites = sum(int(s[0]) * int(s[1]) ** 2 for s in shapes)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value:
+            lib.glasma_batch_destroy(b)
+            self.b = None
+
+    def run(self, steps, graph_chunk=16):
+        self._check(lib.glasma_batch_run(self.b, int(steps), int(graph_chunk)), self.b)
+
+    def set_tiling(self, sites_per_item, grid):
+        self._check(lib.glasma_batch_set_tiling(self.b, int(sites_per_item), int(grid)), self.b)
+
+    def autotune(self, steps=2):
+        import json
+        buf = C.create_string_buffer(8192)
+        self._check(lib.glasma_batch_autotune(self.b, int(steps), buf, 8192), self.b)
+        return json.loads(buf.value.decode())
 
 
 def host_group_op(nc, fp, op, inp, n_out_per_item):

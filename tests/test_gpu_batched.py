@@ -1,0 +1,86 @@
+"""GPU checks of the batched form: several events of different lattice sizes advanced
+together (one launch per step, HIP-graph replay) give bitwise the same states as the
+same events run one by one, for every tiling; event 0 also matches the FP64 oracle."""
+import sys
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice, init_mv
+from _gpu import gpu, lattice_or_skip, state_errs, mv_setup
+
+pytestmark = gpu
+
+SHAPES = [(16, 4), (24, 6), (20, 5), (32, 8)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _events(nc):
+    out = []
+    for e, (nz, nt) in enumerate(SHAPES):
+        w = synth.Workload(f"ev{e}", nc=nc, nz=nz, nt=nt, mu=0.3 + 0.1 * e, sigma=1.5 + 0.5 * e, seed=4100 + e)
+        out.append((w, synth.mv_charges(w.seed, nc, nt, w.mu, w.a_T)))
+    return out
+
+
+def _init(lat, w, rho):
+    lat.init_mv(rho[0], rho[1], m_ir=w.m_ir, sigma=w.sigma, zA=w.zA, zB=w.zB)
+
+
+@pytest.mark.parametrize("nc,fp,reunit", [(3, 64, 0), (3, 32, 8), (2, 64, 0)])
+def test_batched_equals_one_by_one(nc, fp, reunit):
+    pkg = lattice_or_skip()
+    evs = _events(nc)
+    say("case: batched", nc, fp, reunit)
+    n = 13
+    singles = []
+    for w, rho in evs:
+        lat = pkg.Lattice(nc=nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=fp, reunit_every=reunit)
+        _init(lat, w, rho)
+        lat.step(n)
+        singles.append(lat.get_state())
+    for tiling in [(256, 0), (64, 1024), (128, 8)]:
+        b = pkg.Batch(nc, SHAPES, fp=fp, reunit_every=reunit)
+        b.set_tiling(*tiling)
+        for (w, rho), lat in zip(evs, b.events):
+            _init(lat, w, rho)
+        b.run(5, graph_chunk=2)      # two graph replays and one direct step
+        b.run(n - 5, graph_chunk=0)
+        for e, lat in enumerate(b.events):
+            got = lat.get_state()
+            assert got["step"] == n
+            for k in ("U", "E", "rhoA", "rhoB"):
+                assert np.array_equal(got[k], singles[e][k]), (tiling, e, k)
+
+
+def test_batched_event_matches_oracle():
+    pkg = lattice_or_skip()
+    evs = _events(3)
+    b = pkg.Batch(3, SHAPES, fp=64, reunit_every=0)
+    for (w, rho), lat in zip(evs, b.events):
+        _init(lat, w, rho)
+    w, rho = evs[1]
+    p, mv = mv_setup(w)
+    st, _ = init_mv.initial_state(rho[0], rho[1], w.nz, p, mv)
+    for k in range(4):
+        b.run(2, graph_chunk=2)
+        st = lattice.evolve(st, 2)
+        errs = state_errs(b.events[1].get_state(), st)
+        assert max(errs.values()) < 1e-10, (k, errs)
+
+
+def test_autotune_reports_candidates():
+    pkg = lattice_or_skip()
+    b = pkg.Batch(3, SHAPES, fp=32, reunit_every=8)
+    for (w, rho), lat in zip(_events(3), b.events):
+        _init(lat, w, rho)
+    rep = b.autotune(steps=1)
+    assert len(rep["candidates"]) == 12
+    assert rep["chosen"]["sites_per_item"] in (64, 128, 256)
+    say("autotune", rep["chosen"])
+    o = b.events[0].observables()
+    assert o["gauss_rel"] < 1e-4 and o["unitarity"] < 1e-5
