@@ -1,19 +1,24 @@
-"""Throughput of the CPIC leapfrog hot path on one MI355X.
+"""Throughput of the 3+1D Glasma CPIC hot path on one MI355X.
 
-Workload (the method's plain SU(3) configuration): 512 x 64 x 64 lattice, SU(3),
-a_T = 4 a_L, dt = a_L/2, two MV nuclei (mu = 0.5, sigma = 8 a_L, m = 0.2,
+Headline workload (the method's plain SU(3) configuration): 512 x 64 x 64 lattice,
+SU(3), a_T = 4 a_L, dt = a_L/2, two MV nuclei (mu = 0.5, sigma = 8 a_L, m = 0.2,
 Lambda = 10/a_T), initial state built on the GPU.  One step = one leapfrog update of
 every link and E field with the CPIC charge hop on every second step; observables
 (T^{mu nu} slices, Gauss residual, energy) are reduced every 16 steps inside the
 timed region.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line: site-updates/s of the FP64 single-event form (value), the
-roofline of the dominant kernel (the fused leapfrog step) from HIP events on the
-library's stream, the FP32 form, and the oracle timed on the host CPU.
+The JSON line reports site-updates/s of the FP64 single-event form (value), the
+roofline of its dominant kernel (the fused leapfrog step, timed with HIP events on
+the library's stream), the FP32 single-event form, the FP32 batched form (64 events
+of N_z in {128,256,384} x N_T in {32,48,64}, 512 steps, HIP-graph replay, autotuned
+tiling, event-averaged T^{mu nu}(z)), the semi-implicit scheme on the headline
+lattice, and the FP64 CPU oracle timed on the host.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import resource
 import sys
 import time
@@ -24,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "leapfrog_su3_f64_512x64x64_counters.md")
+KERNEL_SOURCES = ["step.hip", "stencil.h", "lattice.h", "group.h"]
 
 
 def algorithmic_bytes_per_site_update(nc, fp, dt_over_aL):
@@ -32,46 +39,112 @@ def algorithmic_bytes_per_site_update(nc, fp, dt_over_aL):
     b = 8 if fp == 64 else 4
     r = 4 if nc == 2 else 18
     ng = nc * nc - 1
-    u = 2 * 3 * r * b
-    e = 2 * 3 * ng * b
-    rho = 2 * 2 * ng * b * dt_over_aL
-    return u + e + rho
+    return 2 * 3 * r * b + 2 * 3 * ng * b + 2 * 2 * ng * b * dt_over_aL
 
 
-def run_gpu(w, fp, steps, warmup, obs_every=16):
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2009_02044_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    try:
+        txt = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    hm = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", txt)
+    if not m or not hm or hm.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def run_plain(w, fp, steps, warmup, obs_every=16, scheme=0, tol=1e-12):
     import torch
     import synth
     import paper_2009_02044_amd as pkg
     lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=fp,
-                      reunit_every=8 if fp == 32 else 0)
+                      reunit_every=8 if fp == 32 else 0, scheme=scheme, max_iter=200, tol=tol)
     rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
     lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
     obs = lat.obs_buffer()
     torch.cuda.synchronize()
     lat.step(warmup)
     torch.cuda.synchronize()
-    # whole hot path: steps + observables every obs_every steps
     t0 = time.perf_counter()
     done = 0
+    iters = []
     while done < steps:
         n = min(obs_every, steps - done)
-        lat.step(n)
+        if scheme == 1:
+            for _ in range(n):
+                lat.step(1)
+                iters.append(lat.last_iterations)
+        else:
+            lat.step(n)
         done += n
         lat.observe(obs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # dominant kernel alone, HIP events on the library's stream
-    st = lat.stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(st)
-    lat.step(steps)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    kern_ms = ev0.elapsed_time(ev1) / steps
+    out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+           "site_updates_per_s": w.sites * steps / wall}
+    if scheme == 0:
+        # the dominant kernel alone, HIP events on the library's stream
+        st = lat.stream
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        lat.step(steps)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        out["kernel_ms"] = ev0.elapsed_time(ev1) / steps
+    else:
+        out["iterations_mean"] = float(np.mean(iters))
     o = pkg.Lattice.unpack_obs(obs, w.nz)
-    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "kernel_ms": kern_ms,
-            "site_updates_per_s": w.sites * steps / wall, "gauss_rel": o["gauss_rel"],
-            "energy": o["energy"], "unitarity": o["unitarity"]}
+    out.update({"gauss_rel": o["gauss_rel"], "energy": o["energy"], "unitarity": o["unitarity"]})
+    return out
+
+
+def run_batched(steps, warmup, graph_chunk=16):
+    """64 events, SU(3) FP32: autotuned tiling, then the timed run; returns throughput and
+    the event-averaged T^{mu nu}(z) per N_z class (transverse means averaged over events)."""
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    evs = synth.batched_events()
+    shapes = [(w.nz, w.nt) for w in evs]
+    b = pkg.Batch(3, shapes, a_T=4.0, a_L=1.0, dt=0.5, fp=32, reunit_every=8)
+
+    def init():
+        for w, lat in zip(evs, b.events):
+            rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+            lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+        b.stream.synchronize()
+
+    init()
+    tune = b.autotune(steps=2)
+    init()
+    b.run(warmup, graph_chunk=0)
+    b.stream.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, graph_chunk=graph_chunk)
+    b.stream.synchronize()
+    wall = time.perf_counter() - t0
+    sums, counts, gauss, unit = {}, {}, 0.0, 0.0
+    for w, lat in zip(evs, b.events):
+        o = lat.observables()
+        sums[w.nz] = sums.get(w.nz, 0) + o["tmunu_z"]
+        counts[w.nz] = counts.get(w.nz, 0) + 1
+        gauss = max(gauss, o["gauss_rel"])
+        unit = max(unit, o["unitarity"])
+    avg = {str(k): (sums[k] / counts[k]).tolist() for k in sorted(sums)}
+    return {"site_updates_per_s": b.sites * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "sites": b.sites, "events": len(evs), "steps": steps, "tiling": tune["chosen"],
+            "gauss_rel_max": gauss, "unitarity_max": unit, "tmunu_z_event_avg_by_nz": avg}
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -99,7 +172,8 @@ def cpu_baseline(w, budget_s=20.0):
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
     return {"value": ws.sites * n / wall, "unit": "site-updates/s",
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"{n} leapfrog steps of a {nz}x{ws.nt}x{ws.nt} slab (SU({ws.nc}), FP64 NumPy)",
+            "sample": f"{n} leapfrog steps of a {nz}x{ws.nt}x{ws.nt} slab of the headline "
+                      f"lattice (SU({ws.nc}), FP64 NumPy)",
             "host_cpus": os.cpu_count()}
 
 
@@ -110,6 +184,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-semi", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=512)
+    ap.add_argument("--semi-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -126,21 +204,40 @@ def main():
         sys.exit(2)
     import synth
     w = synth.PLAIN_SU3
-    r64 = run_gpu(w, 64, args.steps, args.warmup)
+    r64 = run_plain(w, 64, args.steps, args.warmup)
     print(f"[bench] fp64 {w.name}: {r64['site_updates_per_s']:.3e} site-updates/s, "
           f"kernel {r64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
     forms = {}
     if not args.no_fp32:
-        r32 = run_gpu(w, 32, args.steps, args.warmup)
+        r32 = run_plain(w, 32, args.steps, args.warmup)
         b32 = algorithmic_bytes_per_site_update(3, 32, w.dt / w.a_L)
-        forms["fp32_plain"] = {"site_updates_per_s": r32["site_updates_per_s"],
-                               "kernel_ms": r32["kernel_ms"],
-                               "hbm_frac": b32 * w.sites / (r32["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "gauss_rel": r32["gauss_rel"], "unitarity": r32["unitarity"]}
-        print(f"[bench] fp32 {w.name}: {r32['site_updates_per_s']:.3e} site-updates/s", file=sys.stderr,
-              flush=True)
+        forms["fp32_plain"] = {
+            "site_updates_per_s": r32["site_updates_per_s"], "kernel_ms": r32["kernel_ms"],
+            "hbm_frac": b32 * w.sites / (r32["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "gauss_rel": r32["gauss_rel"], "unitarity": r32["unitarity"]}
+        print(f"[bench] fp32 {w.name}: {r32['site_updates_per_s']:.3e} site-updates/s",
+              file=sys.stderr, flush=True)
+    if not args.no_batched:
+        rb = run_batched(args.batched_steps, 8)
+        bb = algorithmic_bytes_per_site_update(3, 32, 0.5)
+        rb["hbm_frac"] = bb * rb["site_updates_per_s"] / 1e9 / HBM_PEAK_GBS
+        rb["vs_fp64_plain"] = rb["site_updates_per_s"] / r64["site_updates_per_s"]
+        forms["fp32_batched"] = rb
+        print(f"[bench] fp32 batched 64 events: {rb['site_updates_per_s']:.3e} site-updates/s "
+              f"({rb['vs_fp64_plain']:.2f}x fp64 plain)", file=sys.stderr, flush=True)
+    if not args.no_semi:
+        for dt in (0.5, 1.0):
+            ws = synth.Workload(w.name, nc=3, nz=w.nz, nt=w.nt, dt=dt, mu=w.mu, sigma=w.sigma,
+                                uv_cut=w.uv_cut, seed=w.seed)
+            rs = run_plain(ws, 64, args.semi_steps, 1, obs_every=4, scheme=1, tol=1e-12)
+            forms[f"semi_implicit_fp64_dt{dt}"] = {
+                "site_updates_per_s": rs["site_updates_per_s"], "ms_per_step": rs["ms_per_step"],
+                "iterations_mean": rs["iterations_mean"], "tol": 1e-12, "gauss_rel": rs["gauss_rel"]}
+            print(f"[bench] semi-implicit dt={dt}: {rs['site_updates_per_s']:.3e} site-updates/s, "
+                  f"{rs['iterations_mean']:.1f} iterations", file=sys.stderr, flush=True)
     bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
-    achieved = bpsu * w.sites / (r64["kernel_ms"] * 1e-3) / 1e9
+    launch_bytes = bpsu * w.sites
+    achieved = launch_bytes / (r64["kernel_ms"] * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w)
@@ -161,9 +258,9 @@ def main():
         "config": {"workload": w.name, "nc": 3, "lattice": [w.nz, w.nt, w.nt], "a_T": w.a_T,
                    "dt": w.dt, "scheme": "leapfrog", "obs_every": 16},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
                      "kernel": "k_leapfrog<Su3<double>,double>", "kernel_ms": r64["kernel_ms"],
-                     "bytes_per_site_update": bpsu},
+                     "bytes_per_site_update": bpsu, "bytes_per_launch": launch_bytes},
         "checks": {"gauss_rel": r64["gauss_rel"], "unitarity": r64["unitarity"]},
         "forms": forms,
         "cpu_baseline": cpu,
