@@ -167,6 +167,59 @@ int glasma_last_iterations(const glasma_ctx* ctx, int32_t* iters);
 /* Current step counter (host value). */
 int glasma_get_step(const glasma_ctx* ctx, int64_t* step);
 
+/* ---- Device state transfer ---------------------------------------------------
+ * Same layout as glasma_init_state / glasma_get_state, but the arrays are device
+ * memory (double): U [3][r_U][V], E [3][n_g][V], rho [n_g][V] at physical positions. */
+
+/* Set the state from device arrays; ampA / ampB (device, [V], may be NULL = 1) scale the
+ * charges of each cell: rho(x) -> amp(x) rho(x).  Resets the step counter to step0 and the
+ * charge storage to offset 0.  Asynchronous. */
+int glasma_set_state_device(glasma_ctx* ctx, const double* U, const double* E, const double* rhoA,
+                            const double* rhoB, const double* ampA, const double* ampB, int64_t step0);
+
+/* Write the state to device arrays (any pointer may be NULL).  Asynchronous. */
+int glasma_get_state_device(glasma_ctx* ctx, double* U, double* E, double* rhoA, double* rhoB);
+
+/* ---- Differentiation form -------------------------------------------------------
+ * Loss of a state (Sec. 4 energy density integrated over the layers z0 <= z < z1 of the
+ * stored fields U(t), E(t - dt/2)):
+ *   L = a_T^2 a_L sum_{z0 <= z < z1} [ 1/2 sum_i |E_i(x)|^2
+ *                                     + sum_{i<j} 2/(a_i a_j)^2 Re Tr(1 - U_{i,j}(x)) ].
+ * Gradients of L after `steps` leapfrog steps with respect to the electric field E and the
+ * charges rho_A, rho_B of the starting state (links of the starting state held fixed), by
+ * the reverse mode of the leapfrog step with the CPIC hop (eqs. lattice_1/2, plaquette and
+ * the hop's transport rule, Sec. 3), differentiated exactly, including the derivative of
+ * the matrix exponential.  The forward pass runs in the context's precision and stores a
+ * checkpoint every ckpt_every steps in the caller's work buffer; the backward pass
+ * recomputes each segment from its checkpoint (bitwise the forward states) and runs the
+ * reverse kernels in double precision.  Reunitarisation (reunit_every) is taken as the
+ * identity in the reverse pass (it moves links by rounding errors only).  The leapfrog
+ * scheme only (scheme 1: GLASMA_E_ARG). */
+
+/* Bytes of the work buffer for `steps` steps with a checkpoint every ckpt_every >= 1. */
+int glasma_adjoint_layout(const glasma_params* p, int32_t steps, int32_t ckpt_every, size_t* work_bytes);
+
+/* Advance the context `steps` steps (as glasma_step) from its current state, storing the
+ * checkpoints in `work` (device, caller-owned, >= glasma_adjoint_layout bytes, kept until
+ * the backward call).  Asynchronous. */
+int glasma_adjoint_forward(glasma_ctx* ctx, int32_t steps, int32_t ckpt_every, void* work, size_t work_bytes);
+
+/* Gradients of scale * L(final state) with respect to the starting state of the last
+ * glasma_adjoint_forward on this context (GLASMA_E_STATE if the context stepped, was set
+ * or reinitialised since, or `work` differs).  Outputs (device double arrays, each may be
+ * NULL): dE0 [3][n_g][V] = dL/dE^a, drhoA0 / drhoB0 [n_g][V] = dL/drho^a at physical
+ * positions, dampA / dampB [V] = sum_a base^a(x) dL/drho^a(x), the derivative with respect
+ * to a per-cell amplitude of the charges (base: device [n_g][V], or NULL for the starting
+ * charges themselves); L (host, may be NULL) receives the unscaled loss.  Does not change
+ * the context's state.  Synchronous when L is given. */
+int glasma_adjoint_backward(glasma_ctx* ctx, int32_t z0, int32_t z1, double scale, void* work, size_t work_bytes,
+                            const double* baseA, const double* baseB, double* L, double* dE0, double* drhoA0,
+                            double* drhoB0, double* dampA, double* dampB);
+
+/* The loss L above at the current state (host result).  Uses the context's work buffer.
+ * Synchronous. */
+int glasma_slab_energy(glasma_ctx* ctx, int32_t z0, int32_t z1, double* L);
+
 /* ---- Batched form ---------------------------------------------------------
  * Many independent events (one MV collision each) of different lattice sizes share
  * one pool of device memory and advance together: one launch per step covers every
@@ -214,6 +267,8 @@ int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t r
  *   4: out = reunitarised link         in = link reals
  *   5: out = [unitarity violation]     in = link reals
  *   6: out = A B (link)                in = [A, B] link reals
+ *   7: out = c int_0^1 exp(-i s c X) L exp(i s c X) ds components, in = [c, X^a, L^a]
+ *        (1 + 2 n_g in; the transpose of the derivative of exp(i c X), double arithmetic)
  * fp = 64 or 32 selects the arithmetic.  n items are processed; in/out are packed
  * item after item.  Returns GLASMA_E_ARG for an unknown op. */
 int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const double* in, double* out);

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libglasma.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "step.hip", "observe.hip", "init.hip", "semi.hip"]
+SOURCES = ["capi.hip", "step.hip", "observe.hip", "init.hip", "semi.hip", "adjoint.hip"]
 
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950",
@@ -32,7 +32,7 @@ def build(verbose=False, extra_flags=(), out=None):
     out = out or OUT
     objdir = OBJ if out == OUT else out + ".objs"
     os.makedirs(objdir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir, list(extra_flags)), SOURCES))
     tmp = out + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]

@@ -1,12 +1,14 @@
 // C-ABI of the library (declared in include/glasma.h): context, argument checks,
 // the integer charge-hop schedule, host <-> device state transfer and dispatch to
 // the templated kernels for (SU(2) | SU(3)) x (double | float).
+#include <algorithm>
 #include <string>
 #include <vector>
 #include <cstring>
 #include <cstdio>
 #include <cmath>
 #include "internal.h"
+#include "adjoint.h"
 #include "../../include/glasma.h"
 
 using namespace gl;
@@ -23,6 +25,12 @@ struct glasma_ctx {
   int64_t hop_p, hop_q;  // dt / a_L = hop_p / hop_q
   bool ready;
   int last_iters;     // iterations of the last semi-implicit step
+  // differentiation form: checkpoints written by glasma_adjoint_forward
+  bool adj_ok;
+  int64_t adj_s0;
+  int32_t adj_steps, adj_every;
+  int adj_off0;
+  const void* adj_work;
   std::string err;
 };
 
@@ -96,7 +104,9 @@ static size_t general_bytes(const glasma_params* p) {
   int ng = p->nc * p->nc - 1;
   size_t ic = ic_work_doubles(g, ng);
   size_t obs = observe_partial_doubles(g) + 4 * (size_t)g.nz + GLASMA_OBS_NSCALARS;
-  return align256((ic > obs ? ic : obs) * sizeof(double));
+  size_t loss = adj_loss_partials(g) + 1;
+  size_t m = ic > obs ? ic : obs;
+  return align256((m > loss ? m : loss) * sizeof(double));
 }
 static SemiRegion semi_region(const glasma_params* p) {
   Geom g = geom_of(p);
@@ -182,6 +192,7 @@ int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream,
   c->hop_q = hq;
   c->ready = false;
   c->last_iters = 0;
+  c->adj_ok = false;
   *out = c;
   return GLASMA_OK;
 }
@@ -237,6 +248,7 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
   c->offA = c->offB = 0;
   c->step = step0;
   c->ready = true;
+  c->adj_ok = false;
   return GLASMA_OK;
 }
 
@@ -249,6 +261,7 @@ int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, con
   HIPCHK(c, hipMemcpyAsync(work + m, rhoT_B, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   McvConst k{mv->m_ir, mv->uv_cut, mv->sigma, mv->zA, mv->zB};
+  c->adj_ok = false;
   c->step = 0;
   c->cur = 0;
   c->offA = c->offB = 0;
@@ -313,10 +326,17 @@ static int semi_step(glasma_ctx* c, const StepConst& sc) {
   });
 }
 
+static int advance(glasma_ctx* c, int32_t n);
+
 int glasma_step(glasma_ctx* c, int32_t n) {
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
   if (n < 0) return fail(c, GLASMA_E_ARG, "n must be >= 0");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state: call glasma_init_state or glasma_init_mv first");
+  c->adj_ok = false;
+  return advance(c, n);
+}
+
+static int advance(glasma_ctx* c, int32_t n) {
   for (int32_t k = 0; k < n; ++k) {
     StepConst sc = step_const(c);
     if (c->p.scheme == 1) {
@@ -349,6 +369,7 @@ int glasma_step(glasma_ctx* c, int32_t n) {
 int glasma_reunitarize(glasma_ctx* c) {
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  c->adj_ok = false;
   dispatch(c, [&]<typename G, typename T>() -> int {
     launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
     return 0;
@@ -475,12 +496,23 @@ static void host_op(int op, int64_t n, const double* in, double* out) {
       case 4: wr_link(G::reunit(rd_link(in)), out); in += R; out += R; break;
       case 5: out[0] = G::unit_violation(rd_link(in)); in += R; out += 1; break;
       case 6: wr_link(G::mul(rd_link(in), rd_link(in + R)), out); in += 2 * R; out += R; break;
+      case 7: {
+        // transpose of the exponential's derivative, always in double (the adjoint's arithmetic)
+        using Gd = typename GroupOf<G::NC, double>::type;
+        typename Gd::Alg e, l;
+        for (int k = 0; k < NG; ++k) { e.c[k] = in[1 + k]; l.c[k] = in[1 + NG + k]; }
+        const typename Gd::Alg r = dexp_transpose<Gd>(e, in[0], l);
+        for (int k = 0; k < NG; ++k) out[k] = r.c[k];
+        in += 1 + 2 * NG;
+        out += NG;
+        break;
+      }
     }
   }
 }
 
 int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const double* in, double* out) {
-  if ((nc != 2 && nc != 3) || (fp != 64 && fp != 32) || op < 0 || op > 6 || n < 0 || (n > 0 && (!in || !out)))
+  if ((nc != 2 && nc != 3) || (fp != 64 && fp != 32) || op < 0 || op > 7 || n < 0 || (n > 0 && (!in || !out)))
     return fail(nullptr, GLASMA_E_ARG, "bad arguments to glasma_host_group_op");
   if (nc == 2 && fp == 64) host_op<Su2<double>>(op, n, in, out);
   else if (nc == 3 && fp == 64) host_op<Su3<double>>(op, n, in, out);
@@ -691,6 +723,7 @@ static void batch_advance(glasma_batch* b, int32_t n) {
     c->offB = (int)((c->offB + h) % c->g.nz);
     c->cur = (c->cur + n) & 1;
     c->step += n;
+    c->adj_ok = false;
   }
 }
 
@@ -785,5 +818,239 @@ int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t r
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
+  return GLASMA_OK;
+}
+
+// ---- differentiation form ------------------------------------------------------------
+// Work buffer of glasma_adjoint_*: [checkpoints: nseg + 1 states][segment: every - 1 states]
+// [lam | ebar | rbarA x2 | rbarB x2 | K | loss partials + 1], each part 256-byte aligned.
+// A state is [U | E | rho_A | rho_B] in the device layout of the context's precision.
+struct AdjRegion {
+  size_t sU, sE, sR, state;   // bytes of the state parts and of one state
+  int64_t nseg, nslots;       // segments, intermediate states per segment
+  size_t ckpt, seg, lam, ebar, rA0, rA1, rB0, rB1, K, part, end;
+};
+static AdjRegion adj_region(const glasma_params* p, int32_t steps, int32_t every) {
+  Geom g = geom_of(p);
+  const size_t e = elem(p);
+  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  AdjRegion a;
+  a.sU = align256(3 * (size_t)r * g.Vp * e);
+  a.sE = align256(3 * (size_t)ng * g.Vp * e);
+  a.sR = align256((size_t)ng * g.Vp * e);
+  a.state = a.sU + a.sE + 2 * a.sR;
+  a.nseg = steps > 0 ? (steps + every - 1) / every : 0;
+  const int64_t seglen = steps < every ? steps : every;
+  a.nslots = seglen > 1 ? seglen - 1 : 0;
+  const size_t alg3 = align256(3 * (size_t)ng * g.V * sizeof(double));
+  const size_t alg1 = align256((size_t)ng * g.V * sizeof(double));
+  a.ckpt = 0;
+  a.seg = a.ckpt + (size_t)(a.nseg + 1) * a.state;
+  a.lam = a.seg + (size_t)a.nslots * a.state;
+  a.ebar = a.lam + alg3;
+  a.rA0 = a.ebar + alg3;
+  a.rA1 = a.rA0 + alg1;
+  a.rB0 = a.rA1 + alg1;
+  a.rB1 = a.rB0 + alg1;
+  a.K = a.rB1 + alg1;
+  a.part = a.K + 2 * alg3;
+  a.end = a.part + align256((adj_loss_partials(g) + 1) * sizeof(double));
+  return a;
+}
+
+struct StatePtr {
+  char *U, *E, *rA, *rB;
+};
+static StatePtr state_at(const AdjRegion& a, char* base) {
+  return StatePtr{base, base + a.sU, base + a.sU + a.sE, base + a.sU + a.sE + a.sR};
+}
+
+// co-moving charge offset at step s, from the offset off0 at step s0
+static int off_at(const glasma_ctx* c, int64_t s0, int off0, int64_t s) {
+  const int64_t h = hop_count(c, s - 1) - hop_count(c, s0 - 1);
+  return (int)(((off0 + h) % c->g.nz + c->g.nz) % c->g.nz);
+}
+
+static int save_state(glasma_ctx* c, const AdjRegion& a, StatePtr d) {
+  const size_t e = elem(&c->p);
+  HIPCHK(c, hipMemcpyAsync(d.U, c->cur ? c->b.U_alt : c->b.U, 3 * (size_t)c->r * c->g.Vp * e,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d.E, c->b.E, 3 * (size_t)c->ng * c->g.Vp * e, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d.rA, c->b.rhoA, (size_t)c->ng * c->g.Vp * e, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d.rB, c->b.rhoB, (size_t)c->ng * c->g.Vp * e, hipMemcpyDeviceToDevice, c->stream));
+  (void)a;
+  return GLASMA_OK;
+}
+
+static int check_adj_args(glasma_ctx* c, int32_t steps, int32_t every) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (c->p.scheme != 0) return fail(c, GLASMA_E_ARG, "the differentiation form covers the leapfrog scheme");
+  if (steps < 0 || every < 1) return fail(c, GLASMA_E_ARG, "steps must be >= 0 and ckpt_every >= 1");
+  return GLASMA_OK;
+}
+
+int glasma_adjoint_layout(const glasma_params* p, int32_t steps, int32_t ckpt_every, size_t* work_bytes) {
+  int rc = check_params(p, nullptr, nullptr);
+  if (rc) return rc;
+  if (!work_bytes) return fail(nullptr, GLASMA_E_ARG, "work_bytes is NULL");
+  if (p->scheme != 0) return fail(nullptr, GLASMA_E_ARG, "the differentiation form covers the leapfrog scheme");
+  if (steps < 0 || ckpt_every < 1) return fail(nullptr, GLASMA_E_ARG, "steps must be >= 0 and ckpt_every >= 1");
+  *work_bytes = adj_region(p, steps, ckpt_every).end;
+  return GLASMA_OK;
+}
+
+int glasma_adjoint_forward(glasma_ctx* c, int32_t steps, int32_t ckpt_every, void* work, size_t work_bytes) {
+  int rc = check_adj_args(c, steps, ckpt_every);
+  if (rc) return rc;
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  if (!work) return fail(c, GLASMA_E_ARG, "work is NULL");
+  const AdjRegion a = adj_region(&c->p, steps, ckpt_every);
+  if (work_bytes < a.end) return fail(c, GLASMA_E_ARG, "work buffer smaller than glasma_adjoint_layout");
+  char* w = (char*)work;
+  const int64_t s0 = c->step;
+  const int off0 = c->offA;
+  for (int64_t k = 0; k < a.nseg; ++k) {
+    if ((rc = save_state(c, a, state_at(a, w + a.ckpt + (size_t)k * a.state)))) return rc;
+    const int64_t n = std::min<int64_t>(ckpt_every, steps - k * ckpt_every);
+    if ((rc = advance(c, (int32_t)n))) return rc;
+  }
+  if ((rc = save_state(c, a, state_at(a, w + a.ckpt + (size_t)a.nseg * a.state)))) return rc;
+  c->adj_ok = true;
+  c->adj_s0 = s0;
+  c->adj_steps = steps;
+  c->adj_every = ckpt_every;
+  c->adj_off0 = off0;
+  c->adj_work = work;
+  return GLASMA_OK;
+}
+
+int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale, void* work, size_t work_bytes,
+                            const double* baseA, const double* baseB, double* L, double* dE0, double* drhoA0,
+                            double* drhoB0, double* dampA, double* dampB) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (!c->adj_ok || work != c->adj_work || c->step != c->adj_s0 + c->adj_steps)
+    return fail(c, GLASMA_E_STATE, "glasma_adjoint_forward with this work buffer must come right before");
+  if (z0 < 0 || z1 > c->g.nz || z0 >= z1) return fail(c, GLASMA_E_ARG, "need 0 <= z0 < z1 <= nz");
+  const int32_t steps = c->adj_steps, every = c->adj_every;
+  const AdjRegion a = adj_region(&c->p, steps, every);
+  if (work_bytes < a.end) return fail(c, GLASMA_E_ARG, "work buffer smaller than glasma_adjoint_layout");
+  char* w = (char*)work;
+  double* lam = (double*)(w + a.lam);
+  double* ebar = (double*)(w + a.ebar);
+  double* rA[2] = {(double*)(w + a.rA0), (double*)(w + a.rA1)};
+  double* rB[2] = {(double*)(w + a.rB0), (double*)(w + a.rB1)};
+  double* K = (double*)(w + a.K);
+  double* part = (double*)(w + a.part);
+  double* Lout = part + adj_loss_partials(c->g);
+  const double sp[3] = {c->p.a_T, c->p.a_T, c->p.a_L};
+  const int64_t s0 = c->adj_s0;
+  const int off0 = c->adj_off0;
+  auto ckpt = [&](int64_t k) { return state_at(a, w + a.ckpt + (size_t)k * a.state); };
+  int cur = 0;
+  int rc = dispatch(c, [&]<typename G, typename T>() -> int {
+    const StatePtr fin = ckpt(a.nseg);
+    launch_adj_loss<G, T>((const T*)fin.U, (const T*)fin.E, c->g, sp, z0, z1, scale, lam, ebar, rA[0], rB[0], part,
+                          Lout, c->stream);
+    const size_t nE = 3 * (size_t)c->ng * c->g.Vp * sizeof(T), nR = (size_t)c->ng * c->g.Vp * sizeof(T);
+    for (int64_t k = a.nseg - 1; k >= 0; --k) {
+      const int64_t sk = s0 + k * every;
+      const int64_t len = std::min<int64_t>(every, steps - k * every);
+      auto slot = [&](int64_t m) {
+        if (m == 0) return ckpt(k);
+        if (m == len) return ckpt(k + 1);
+        return state_at(a, w + a.seg + (size_t)(m - 1) * a.state);
+      };
+      // recompute the segment's states (bitwise those of the forward pass)
+      for (int64_t m = 0; m + 1 < len; ++m) {
+        const StatePtr x = slot(m), y = slot(m + 1);
+        HIPCHK(c, hipMemcpyAsync(y.E, x.E, nE, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(y.rA, x.rA, nR, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(y.rB, x.rB, nR, hipMemcpyDeviceToDevice, c->stream));
+        StepConst sc;
+        sc.a[0] = sp[0]; sc.a[1] = sp[1]; sc.a[2] = sp[2];
+        sc.dt = c->p.dt;
+        sc.hop = is_hop(c, sk + m) ? 1 : 0;
+        sc.offA = sc.offB = off_at(c, s0, off0, sk + m);
+        sc.scheme = 0;
+        launch_leapfrog<G, T>((const T*)x.U, (T*)y.U, (T*)y.E, (T*)y.rA, (T*)y.rB, c->g, sc, c->stream);
+        if (c->p.reunit_every > 0 && (sk + m + 1) % c->p.reunit_every == 0) launch_reunit<G, T>((T*)y.U, c->g, c->stream);
+      }
+      for (int64_t m = len - 1; m >= 0; --m) {
+        const int64_t s = sk + m;
+        const StatePtr x = slot(m), y = slot(m + 1);
+        const bool hop = is_hop(c, s);
+        launch_adj_step<G, T>((const T*)x.U, (const T*)y.E, (const T*)y.rA, (const T*)x.rB,
+                              off_at(c, s0, off0, s + 1), off_at(c, s0, off0, s), hop, c->g, sp, c->p.dt, lam, ebar,
+                              K, rA[cur], rB[cur], rA[cur ^ 1], rB[cur ^ 1], c->stream);
+        if (hop) cur ^= 1;
+      }
+    }
+    const size_t n3 = 3 * (size_t)c->ng * c->g.V * sizeof(double), n1 = (size_t)c->ng * c->g.V * sizeof(double);
+    if (dE0) HIPCHK(c, hipMemcpyAsync(dE0, ebar, n3, hipMemcpyDeviceToDevice, c->stream));
+    if (drhoA0) HIPCHK(c, hipMemcpyAsync(drhoA0, rA[cur], n1, hipMemcpyDeviceToDevice, c->stream));
+    if (drhoB0) HIPCHK(c, hipMemcpyAsync(drhoB0, rB[cur], n1, hipMemcpyDeviceToDevice, c->stream));
+    const StatePtr c0 = ckpt(0);
+    if (dampA) launch_amp<G, T>(rA[cur], baseA, (const T*)c0.rA, off0, 0, c->g, dampA, c->stream);
+    if (dampB) launch_amp<G, T>(rB[cur], baseB, (const T*)c0.rB, off0, 1, c->g, dampB, c->stream);
+    return GLASMA_OK;
+  });
+  if (rc) return rc;
+  HIPCHK(c, hipGetLastError());
+  if (L) {
+    HIPCHK(c, hipMemcpyAsync(L, Lout, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return GLASMA_OK;
+}
+
+int glasma_slab_energy(glasma_ctx* c, int32_t z0, int32_t z1, double* L) {
+  if (!c || !L) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  if (z0 < 0 || z1 > c->g.nz || z0 >= z1) return fail(c, GLASMA_E_ARG, "need 0 <= z0 < z1 <= nz");
+  const double sp[3] = {c->p.a_T, c->p.a_T, c->p.a_L};
+  double* part = (double*)c->b.work;
+  double* out = part + adj_loss_partials(c->g);
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_adj_loss<G, T>(cur_U<T>(c), (const T*)c->b.E, c->g, sp, z0, z1, 1.0, nullptr, nullptr, nullptr, nullptr,
+                          part, out, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(L, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GLASMA_OK;
+}
+
+int glasma_set_state_device(glasma_ctx* c, const double* U, const double* E, const double* rhoA, const double* rhoB,
+                            const double* ampA, const double* ampB, int64_t step0) {
+  if (!c || !U || !E || !rhoA || !rhoB) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (step0 < 0) return fail(c, GLASMA_E_ARG, "step0 must be >= 0");
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_pack<G, T>(U, nullptr, (T*)c->b.U, c->g, 3, c->r, c->stream);
+    launch_pack<G, T>(E, nullptr, (T*)c->b.E, c->g, 3, c->ng, c->stream);
+    launch_pack<G, T>(rhoA, ampA, (T*)c->b.rhoA, c->g, 1, c->ng, c->stream);
+    launch_pack<G, T>(rhoB, ampB, (T*)c->b.rhoB, c->g, 1, c->ng, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  c->cur = 0;
+  c->offA = c->offB = 0;
+  c->step = step0;
+  c->ready = true;
+  c->adj_ok = false;
+  return GLASMA_OK;
+}
+
+int glasma_get_state_device(glasma_ctx* c, double* U, double* E, double* rhoA, double* rhoB) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    if (U) launch_unpack<G, T>(cur_U<T>(c), U, c->g, 3, c->r, 0, 0, c->stream);
+    if (E) launch_unpack<G, T>((const T*)c->b.E, E, c->g, 3, c->ng, 0, 0, c->stream);
+    if (rhoA) launch_unpack<G, T>((const T*)c->b.rhoA, rhoA, c->g, 1, c->ng, c->offA, 1, c->stream);
+    if (rhoB) launch_unpack<G, T>((const T*)c->b.rhoB, rhoB, c->g, 1, c->ng, c->offB, 2, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
   return GLASMA_OK;
 }

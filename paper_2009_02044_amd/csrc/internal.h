@@ -80,4 +80,26 @@ template <typename G, typename T>
 void launch_gauss_charges(const T* U, const T* E, const T* F2, double scale, T* rhoA, T* rhoB, const Geom& g,
                           const StepConst& c, hipStream_t st);
 
+// Differentiation form (adjoint.hip): cotangents in double, plain [dir][a][V] arrays.
+// Loss of layers [z0, z1) of the state (U, E) into out[0] (partial needs adj_loss_partials
+// doubles); with lam != null also the seed cotangents scale * dL/d(state).
+size_t adj_loss_partials(const Geom& g);
+template <typename G, typename S>
+void launch_adj_loss(const S* U, const S* E, const Geom& g, const double* a, int z0, int z1, double scale,
+                     double* lam, double* ebar, double* rA, double* rB, double* partial, double* out, hipStream_t st);
+// One reverse step: state s (U0, rhoB0 at offset offB0), E1 and rhoA1 (offset offA1) of
+// state s + 1; K holds 6 n_g V doubles; on hop steps the charge cotangents move from
+// (rAin, rBin) to (rAout, rBout).
+template <typename G, typename S>
+void launch_adj_step(const S* U0, const S* E1, const S* rhoA1, const S* rhoB0, int offA1, int offB0, bool hop,
+                     const Geom& g, const double* a, double dt, double* lam, double* ebar, double* K,
+                     const double* rAin, const double* rBin, double* rAout, double* rBout, hipStream_t st);
+template <typename G, typename S>
+void launch_pack(const double* src, const double* amp, S* dst, const Geom& g, int ndir, int width, hipStream_t st);
+template <typename G, typename S>
+void launch_unpack(const S* src, double* dst, const Geom& g, int ndir, int width, int off, int kind, hipStream_t st);
+template <typename G, typename S>
+void launch_amp(const double* rbar, const double* base, const S* rho, int off, int which, const Geom& g, double* out,
+                hipStream_t st);
+
 }  // namespace gl

@@ -8,6 +8,14 @@ from . import _lib
 from ._lib import lib, check, dptr
 
 
+def _device(device):
+    """torch.device with an explicit index (tensors report cuda:k)."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 class Lattice:
     """One event: SU(nc) links, E field and the two nuclei's CPIC charges on an
     nz x nt x nt lattice held in caller-owned (torch) device buffers."""
@@ -16,10 +24,10 @@ class Lattice:
                  reunit_every=0, max_iter=50, tol=0.0, device="cuda", _ctx=None, _stream=None):
         if _ctx is not None:      # a view of an event owned by a Batch
             self.params = _lib.Params(nc, nz, nt, a_T, a_L, dt, fp, scheme, reunit_every, max_iter, tol)
-            self.device = torch.device(device)
             self.stream = _stream
             self.ctx = _ctx
             self._owned = False
+            self.device = _device(device)
             self._set_dims(nc, nz, nt, fp)
             return
         if not torch.cuda.is_available():
@@ -28,7 +36,7 @@ class Lattice:
         sizes = (C.c_size_t * 6)()
         check(lib.glasma_layout(C.byref(self.params), sizes))
         self.sizes = list(sizes)
-        self.device = torch.device(device)
+        self.device = _device(device)
         self._bufs = [torch.empty(max(int(s), 1), dtype=torch.uint8, device=self.device) for s in self.sizes]
         b = _lib.Buffers(*[t.data_ptr() for t in self._bufs])
         self.stream = torch.cuda.current_stream(self.device)
@@ -116,6 +124,63 @@ class Lattice:
         return {"tmunu_z": t, "gauss_rel": vals[0].value, "gauss_max": vals[1].value,
                 "energy": vals[2].value, "unitarity": vals[3].value}
 
+    # -- device state transfer (plain double layout of the C-ABI) -------------
+    def _dev(self, t, shape, name):
+        if t is None:
+            return None
+        if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def set_state_device(self, U, E, rhoA, rhoB, ampA=None, ampB=None, step0=0):
+        """Device float64 tensors U (3, r_U, V), E (3, n_g, V), rho (n_g, V); amp (V,) scales
+        the charges of each cell."""
+        self._chk(lib.glasma_set_state_device(
+            self.ctx, self._dev(U, (3, self.r, self.V), "U"), self._dev(E, (3, self.ng, self.V), "E"),
+            self._dev(rhoA, (self.ng, self.V), "rhoA"), self._dev(rhoB, (self.ng, self.V), "rhoB"),
+            self._dev(ampA, (self.V,), "ampA"), self._dev(ampB, (self.V,), "ampB"), int(step0)))
+
+    def get_state_device(self):
+        f = dict(dtype=torch.float64, device=self.device)
+        out = {"U": torch.empty(3, self.r, self.V, **f), "E": torch.empty(3, self.ng, self.V, **f),
+               "rhoA": torch.empty(self.ng, self.V, **f), "rhoB": torch.empty(self.ng, self.V, **f)}
+        self._chk(lib.glasma_get_state_device(self.ctx, *[C.c_void_p(out[k].data_ptr())
+                                                          for k in ("U", "E", "rhoA", "rhoB")]))
+        return out
+
+    # -- differentiation form ----------------------------------------------------
+    def slab_energy(self, z0, z1):
+        """Electric + magnetic energy of layers [z0, z1) of the current state (glasma_slab_energy)."""
+        v = C.c_double()
+        self._chk(lib.glasma_slab_energy(self.ctx, int(z0), int(z1), C.byref(v)))
+        return v.value
+
+    def adjoint_work(self, steps, ckpt_every):
+        n = C.c_size_t()
+        check(lib.glasma_adjoint_layout(C.byref(self.params), int(steps), int(ckpt_every), C.byref(n)))
+        return torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+
+    def adjoint_forward(self, steps, ckpt_every, work):
+        self._chk(lib.glasma_adjoint_forward(self.ctx, int(steps), int(ckpt_every), C.c_void_p(work.data_ptr()),
+                                             work.numel()))
+
+    def adjoint_backward(self, z0, z1, work, scale=1.0, baseA=None, baseB=None):
+        """Gradients of scale * L with respect to the state before the last adjoint_forward:
+        dE0 (3, n_g, V), drhoA0 / drhoB0 (n_g, V), dampA / dampB (V,); L (unscaled)."""
+        f = dict(dtype=torch.float64, device=self.device)
+        out = {"dE0": torch.empty(3, self.ng, self.V, **f), "drhoA0": torch.empty(self.ng, self.V, **f),
+               "drhoB0": torch.empty(self.ng, self.V, **f), "dampA": torch.empty(self.V, **f),
+               "dampB": torch.empty(self.V, **f)}
+        L = C.c_double()
+        self._chk(lib.glasma_adjoint_backward(
+            self.ctx, int(z0), int(z1), float(scale), C.c_void_p(work.data_ptr()), work.numel(),
+            self._dev(baseA, (self.ng, self.V), "baseA"), self._dev(baseB, (self.ng, self.V), "baseB"),
+            C.byref(L), *[C.c_void_p(out[k].data_ptr()) for k in ("dE0", "drhoA0", "drhoB0", "dampA", "dampB")]))
+        out["L"] = L.value
+        return out
+
     @staticmethod
     def unpack_obs(buf, nz):
         h = buf.detach().cpu().numpy()
@@ -141,7 +206,7 @@ class Batch:
         self.nt = (C.c_int32 * n)(*[int(s[1]) for s in shapes])
         size = C.c_size_t()
         check_batch(lib.glasma_batch_layout(C.byref(self.params), n, self.nz, self.nt, C.byref(size)))
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.pool = torch.empty(size.value, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.Stream(self.device)
         self.b = C.c_void_p()
@@ -173,6 +238,30 @@ class Batch:
         buf = C.create_string_buffer(8192)
         self._check(lib.glasma_batch_autotune(self.b, int(steps), buf, 8192), self.b)
         return json.loads(buf.value.decode())
+
+
+class SlabEnergy(torch.autograd.Function):
+    """L(E0, ampA, ampB): energy of layers [z0, z1) after `steps` leapfrog steps of `lat`
+    from the state (U0, E0, ampA * rhoA, ampB * rhoB) at step 0, with U0 held fixed.
+    Forward: glasma_adjoint_forward (checkpoint every ckpt_every steps) and
+    glasma_slab_energy; backward: glasma_adjoint_backward.  E0 (3, n_g, V), amp (V,),
+    U0 (3, r_U, V) and the base charges (n_g, V) are float64 device tensors."""
+
+    @staticmethod
+    def forward(ctx, E0, ampA, ampB, lat, U0, rhoA, rhoB, steps, ckpt_every, z0, z1):
+        lat.set_state_device(U0, E0.contiguous(), rhoA, rhoB, ampA.contiguous(), ampB.contiguous(), 0)
+        work = lat.adjoint_work(steps, ckpt_every)
+        lat.adjoint_forward(steps, ckpt_every, work)
+        L = lat.slab_energy(z0, z1)
+        ctx.lat, ctx.work, ctx.slab = lat, work, (z0, z1)
+        ctx.save_for_backward(rhoA, rhoB)
+        return torch.tensor(L, dtype=torch.float64, device=E0.device)
+
+    @staticmethod
+    def backward(ctx, gL):
+        rhoA, rhoB = ctx.saved_tensors
+        g = ctx.lat.adjoint_backward(ctx.slab[0], ctx.slab[1], ctx.work, scale=float(gL), baseA=rhoA, baseB=rhoB)
+        return (g["dE0"], g["dampA"], g["dampB"]) + (None,) * 8
 
 
 def host_group_op(nc, fp, op, inp, n_out_per_item):

@@ -118,3 +118,25 @@ def test_device_log_proj_transport_reunit(nc):
     assert uv.max() < 1e-14
     prod = host_group_op(nc, 64, 6, np.concatenate([_link_reals(U), _link_reals(U[::-1])], axis=1), r)
     np.testing.assert_allclose(_reals_link(prod, nc), U @ U[::-1], atol=1e-14)
+
+
+@pytest.mark.parametrize("nc", [2, 3])
+def test_device_exp_derivative_transpose_matches_expm_frechet(nc):
+    """op 7 (the reverse-mode kernel's exponential step): T(L)^b = <L, xi(t^b)> with the
+    left derivative xi(Y) = -i D exp(i c X)[i c Y] exp(-i c X) from scipy's expm_frechet."""
+    from paper_2009_02044_amd import host_group_op
+    ng = nc * nc - 1
+    t = su.generators(nc)
+    cases = [(0.3, 0.5), (2.0, 1.0), (4.0, 2.5), (1.0, 0.0), (0.5, 1e-5)]
+    for k, (c, amp) in enumerate(cases):
+        X = synth.normal(30 + k, (ng,), amp)
+        Lm = synth.normal(40 + k, (ng,), 1.0)
+        got = host_group_op(nc, 64, 7, np.concatenate([[c], X, Lm])[None, :], ng)[0]
+        A = 1j * c * su.from_components(X, nc)
+        W = sla.expm(A)
+        ref = np.empty(ng)
+        for b in range(ng):
+            _, D = sla.expm_frechet(A, 1j * c * t[b])
+            xi = -1j * D @ W.conj().T
+            ref[b] = np.sum(Lm * su.to_components(xi))
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, c), (c, amp, got, ref)
