@@ -12,7 +12,10 @@ roofline of its dominant kernel (the fused leapfrog step, timed with HIP events 
 the library's stream), the FP32 single-event form, the FP32 batched form (64 events
 of N_z in {128,256,384} x N_T in {32,48,64}, 512 steps, HIP-graph replay, autotuned
 tiling, event-averaged T^{mu nu}(z)), the semi-implicit scheme on the headline
-lattice, and the FP64 CPU oracle timed on the host.
+lattice, the differentiation form (gradient of the central-slab energy after 256 steps of
+a 256 x 32 x 32 lattice, FP32 forward with checkpoints every 32 steps, FP64 reverse pass),
+optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and the
+FP64 CPU oracle timed on the host.
 """
 import argparse
 import hashlib
@@ -147,6 +150,78 @@ def run_batched(steps, warmup, graph_chunk=16):
             "gauss_rel_max": gauss, "unitarity_max": unit, "tmunu_z_event_avg_by_nz": avg}
 
 
+def run_adjoint(w, steps, every, fp=32):
+    """Differentiation form: forward pass with a checkpoint every `every` steps, then the
+    reverse pass (segment recompute + reverse kernels) for the gradient of the central
+    16-layer energy with respect to E0 and the per-cell charge amplitudes."""
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=fp,
+                      reunit_every=8 if fp == 32 else 0)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    s0 = lat.get_state_device()
+    work = lat.adjoint_work(steps, every)
+    z0, z1 = w.nz // 2 - 8, w.nz // 2 + 8
+    times = []
+    for rep in range(2):                       # the first pass warms up
+        lat.set_state_device(s0["U"], s0["E"], s0["rhoA"], s0["rhoB"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.adjoint_forward(steps, every, work)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = lat.adjoint_backward(z0, z1, work)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = times[-1]
+    return {"site_updates_per_s": w.sites * steps / (fwd + bwd), "forward_s": fwd, "backward_s": bwd,
+            "backward_over_forward": bwd / fwd, "workload": w.name, "steps": steps, "ckpt_every": every,
+            "forward_dtype": "f32" if fp == 32 else "f64", "adjoint_dtype": "f64",
+            "work_bytes": int(work.numel()), "loss": g["L"],
+            "grad_norm_E0": float(g["dE0"].norm()), "grad_norm_ampA": float(g["dampA"].norm())}
+
+
+def run_precision(w, steps, every=256):
+    """Precision form: FP32 storage and arithmetic with FP64 reunitarisation every 8 steps,
+    against the FP64 GPU run from the same initial state; relative errors of the per-layer
+    eps, p_L, p_T and of their totals at intervals of `every` steps."""
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    series = {}
+    for fp in (64, 32):
+        lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=fp,
+                          reunit_every=8 if fp == 32 else 0)
+        lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = []
+        for k in range(steps // every):
+            lat.step(every)
+            obs.append(lat.observables())
+            print(f"[bench] precision fp{fp}: step {(k + 1) * every}", file=sys.stderr, flush=True)
+        series[fp] = {"obs": obs, "wall_s": time.perf_counter() - t0}
+        del lat
+        torch.cuda.empty_cache()
+    rows = []
+    for k in range(steps // every):
+        a, b = series[32]["obs"][k], series[64]["obs"][k]
+        row = {"step": (k + 1) * every}
+        for q, name in enumerate(("eps", "pL", "pT")):
+            s32, s64 = a["tmunu_z"][q], b["tmunu_z"][q]
+            row[f"{name}_slices_max_rel"] = float(np.abs(s32 - s64).max() / np.abs(s64).max())
+            row[f"{name}_total_rel"] = float(abs(s32.sum() - s64.sum()) / abs(s64.sum()))
+        row["gauss_rel_fp32"] = a["gauss_rel"]
+        row["unitarity_fp32"] = a["unitarity"]
+        rows.append(row)
+    return {"workload": w.name, "lattice": [w.nz, w.nt, w.nt], "steps": steps, "reunit_every": 8,
+            "fp64_wall_s": series[64]["wall_s"], "fp32_wall_s": series[32]["wall_s"], "rows": rows}
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload: a 64-layer slab of the
     beam axis at the full transverse size, stepped until ~budget_s of CPU time."""
@@ -188,6 +263,10 @@ def main():
     ap.add_argument("--no-semi", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=512)
     ap.add_argument("--semi-steps", type=int, default=8)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
+    ap.add_argument("--precision-steps", type=int, default=2048)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -235,6 +314,15 @@ def main():
                 "iterations_mean": rs["iterations_mean"], "tol": 1e-12, "gauss_rel": rs["gauss_rel"]}
             print(f"[bench] semi-implicit dt={dt}: {rs['site_updates_per_s']:.3e} site-updates/s, "
                   f"{rs['iterations_mean']:.1f} iterations", file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        wa = synth.ADJOINT_SU3
+        ra = run_adjoint(wa, wa.steps, 32)
+        forms["adjoint_fp32_fwd_fp64_rev"] = ra
+        print(f"[bench] adjoint {wa.name}: forward {ra['forward_s']:.3f} s, backward {ra['backward_s']:.3f} s",
+              file=sys.stderr, flush=True)
+    if args.precision_study:
+        wp = synth.PRECISION_SU3
+        forms["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)
     bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
     launch_bytes = bpsu * w.sites
     achieved = launch_bytes / (r64["kernel_ms"] * 1e-3) / 1e9
