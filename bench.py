@@ -37,10 +37,11 @@ KERNEL_SOURCES = ["step.hip", "stencil.h", "lattice.h", "group.h"]
 
 
 def algorithmic_bytes_per_site_update(nc, fp, dt_over_aL):
-    """Minimum HBM traffic of one site-update: read + write U and E once, plus read +
-    write of both charge populations on hop steps (a fraction dt/a_L of the steps)."""
+    """Minimum HBM traffic of one site-update: read + write U (stored form: SU(2) 4 reals,
+    SU(3) rows 0 and 1 = 12 reals) and E once, plus read + write of both charge populations
+    on hop steps (a fraction dt/a_L of the steps)."""
     b = 8 if fp == 64 else 4
-    r = 4 if nc == 2 else 18
+    r = 4 if nc == 2 else 12
     ng = nc * nc - 1
     return 2 * 3 * r * b + 2 * 3 * ng * b + 2 * 2 * ng * b * dt_over_aL
 

@@ -28,9 +28,11 @@
  * Device buffers hold the same fields in the context's precision (fp = 64: double,
  * fp = 32: float) in a tiled layout: per direction, records of 64 consecutive sites
  * in which the components are grouped in 16-byte chunks, one row of 64 chunks per
- * group; the site count is padded to Vp = 64 ceil(V/64).  The charge
- * buffers are stored co-moving with their nucleus.  Read and write device state only
- * through glasma_init_state / glasma_get_state.
+ * group; the site count is padded to Vp = 64 ceil(V/64).  SU(3) links are stored by
+ * their first two rows (r_S = 12 reals; the third row of a special unitary matrix is
+ * conj(row 0 x row 1) and is rebuilt on every load), SU(2) links by r_S = 4 reals.  The
+ * charge buffers are stored co-moving with their nucleus.  Read and write device state
+ * only through glasma_init_state / glasma_get_state (or their device-array variants).
  *
  * Memory: the caller allocates every device buffer (sizes from glasma_layout) and
  * keeps it alive until glasma_destroy; the library never allocates or frees device
@@ -74,7 +76,7 @@ typedef struct {
 
 /* Device buffers (caller-owned; sizes in bytes from glasma_layout, same order). */
 typedef struct {
-  void* U;      /* links at the current time, 3 * r_U * Vp reals (r_U = 4 or 18) */
+  void* U;      /* links at the current time, 3 * r_S * Vp reals (r_S = 4 or 12) */
   void* U_alt;  /* second link buffer of the same size (the step writes into it) */
   void* E;      /* electric field, 3 * n_g * Vp reals */
   void* rhoA;   /* charges of nucleus A, n_g * Vp reals (co-moving storage) */

@@ -294,7 +294,8 @@ __global__ void __launch_bounds__(256) k_adj_r2(const S* __restrict__ U, const S
 }
 
 // ---- device state transfer (plain double arrays <-> tiled storage) --------------------
-// src/dst: [dir][comp][V] double; charges at physical layer z live in slot zslot(z).
+// Algebra fields (width n_g): src/dst [dir][comp][V] double; charges at physical layer z
+// live in their co-moving slot.
 template <typename S, int W>
 __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ src, const double* __restrict__ amp,
                                               S* __restrict__ dst, Geom g, int ndir) {
@@ -320,6 +321,44 @@ __global__ void __launch_bounds__(256) k_unpack(const S* __restrict__ src, doubl
   double v[W];
   load_comps<double, S, W>(v, field_dir(src, d, W, g.Vp), site_index(g, x, y, zs));
   for (int k = 0; k < W; ++k) dst[((int64_t)d * W + k) * g.V + s] = v[k];
+}
+
+// Links: plain [dir][host reals][V] double <-> the storage of load_link / store_link.
+template <typename Gs, typename S>
+__global__ void __launch_bounds__(256) k_pack_links(const double* __restrict__ src, S* __restrict__ dst, Geom g) {
+  using L = typename Gs::Link;
+  constexpr int R = Gs::R;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  const int d = blockIdx.y;
+  double v[R];
+  for (int k = 0; k < R; ++k) v[k] = src[((int64_t)d * R + k) * g.V + s];
+  L l;
+  if constexpr (R == 4) {
+    for (int k = 0; k < 4; ++k) l.q[k] = v[k];
+  } else {
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) { l.re[r][k] = v[2 * (3 * r + k)]; l.im[r][k] = v[2 * (3 * r + k) + 1]; }
+  }
+  store_link(l, dst, d, s, g.Vp);
+}
+template <typename Gs, typename S>
+__global__ void __launch_bounds__(256) k_unpack_links(const S* __restrict__ src, double* __restrict__ dst, Geom g) {
+  using L = typename Gs::Link;
+  constexpr int R = Gs::R;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  const int d = blockIdx.y;
+  L l;
+  load_link(l, src, d, s, g.Vp);
+  double v[R];
+  if constexpr (R == 4) {
+    for (int k = 0; k < 4; ++k) v[k] = l.q[k];
+  } else {
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) { v[2 * (3 * r + k)] = l.re[r][k]; v[2 * (3 * r + k) + 1] = l.im[r][k]; }
+  }
+  for (int k = 0; k < R; ++k) dst[((int64_t)d * R + k) * g.V + s] = v[k];
 }
 
 // dL/d alpha(x) = sum_a base^a(x) rbar^a(x) (per-cell amplitude of the charges); base in the
@@ -385,18 +424,24 @@ void launch_adj_step(const S* U0, const S* E1, const S* rhoA1, const S* rhoB0, i
 template <typename G, typename S>
 void launch_pack(const double* src, const double* amp, S* dst, const Geom& g, int ndir, int width, hipStream_t stm) {
   const dim3 grid(nblocks(g), (unsigned)ndir);
-  if (width == 4) hipLaunchKernelGGL((k_pack<S, 4>), grid, dim3(256), 0, stm, src, amp, dst, g, ndir);
-  else if (width == 18) hipLaunchKernelGGL((k_pack<S, 18>), grid, dim3(256), 0, stm, src, amp, dst, g, ndir);
-  else if (width == 3) hipLaunchKernelGGL((k_pack<S, 3>), grid, dim3(256), 0, stm, src, amp, dst, g, ndir);
+  if (width == 3) hipLaunchKernelGGL((k_pack<S, 3>), grid, dim3(256), 0, stm, src, amp, dst, g, ndir);
   else hipLaunchKernelGGL((k_pack<S, 8>), grid, dim3(256), 0, stm, src, amp, dst, g, ndir);
 }
 template <typename G, typename S>
 void launch_unpack(const S* src, double* dst, const Geom& g, int ndir, int width, int off, int kind, hipStream_t stm) {
   const dim3 grid(nblocks(g), (unsigned)ndir);
-  if (width == 4) hipLaunchKernelGGL((k_unpack<S, 4>), grid, dim3(256), 0, stm, src, dst, g, off, kind);
-  else if (width == 18) hipLaunchKernelGGL((k_unpack<S, 18>), grid, dim3(256), 0, stm, src, dst, g, off, kind);
-  else if (width == 3) hipLaunchKernelGGL((k_unpack<S, 3>), grid, dim3(256), 0, stm, src, dst, g, off, kind);
+  if (width == 3) hipLaunchKernelGGL((k_unpack<S, 3>), grid, dim3(256), 0, stm, src, dst, g, off, kind);
   else hipLaunchKernelGGL((k_unpack<S, 8>), grid, dim3(256), 0, stm, src, dst, g, off, kind);
+}
+template <typename G, typename S>
+void launch_pack_links(const double* src, S* dst, const Geom& g, hipStream_t stm) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  hipLaunchKernelGGL((k_pack_links<Gd, S>), dim3(nblocks(g), 3), dim3(256), 0, stm, src, dst, g);
+}
+template <typename G, typename S>
+void launch_unpack_links(const S* src, double* dst, const Geom& g, hipStream_t stm) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  hipLaunchKernelGGL((k_unpack_links<Gd, S>), dim3(nblocks(g), 3), dim3(256), 0, stm, src, dst, g);
 }
 template <typename G, typename S>
 void launch_amp(const double* rbar, const double* base, const S* rho, int off, int which, const Geom& g, double* out,
@@ -413,6 +458,8 @@ void launch_amp(const double* rbar, const double* base, const S* rho, int off, i
                                       const double*, double*, double*, hipStream_t);                              \
   template void launch_pack<G, S>(const double*, const double*, S*, const Geom&, int, int, hipStream_t);          \
   template void launch_unpack<G, S>(const S*, double*, const Geom&, int, int, int, int, hipStream_t);             \
+  template void launch_pack_links<G, S>(const double*, S*, const Geom&, hipStream_t);                             \
+  template void launch_unpack_links<G, S>(const S*, double*, const Geom&, hipStream_t);                           \
   template void launch_amp<G, S>(const double*, const double*, const S*, int, int, const Geom&, double*,          \
                                  hipStream_t);
 GL_ADJ_INST(Su2<double>, double)

@@ -18,7 +18,8 @@ struct glasma_ctx {
   glasma_buffers b;
   hipStream_t stream;
   Geom g;
-  int ng, r;
+  int ng, r;          // n_g; reals per link in host arrays (4 or 18)
+  int rs;             // reals per link in device storage (4 or 12)
   int64_t step;
   int cur;            // 0: links live in b.U, 1: in b.U_alt
   int offA, offB;     // co-moving charge storage offsets (mod nz)
@@ -64,6 +65,8 @@ static int64_t hop_count(const glasma_ctx* c, int64_t s) {
 static bool is_hop(const glasma_ctx* c, int64_t s) { return hop_count(c, s) > hop_count(c, s - 1); }
 
 static size_t elem(const glasma_params* p) { return p->fp == 64 ? 8 : 4; }
+// reals per link in device storage
+static int stored_width(const glasma_params* p) { return p->nc == 2 ? 4 : SU3_STORED; }
 
 static int check_params(const glasma_params* p, int64_t* hp, int64_t* hq) {
   if (!p) return fail(nullptr, GLASMA_E_ARG, "params is NULL");
@@ -111,7 +114,7 @@ static size_t general_bytes(const glasma_params* p) {
 static SemiRegion semi_region(const glasma_params* p) {
   Geom g = geom_of(p);
   const size_t e = p->fp == 64 ? 8 : 4;
-  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  const int ng = p->nc * p->nc - 1, r = stored_width(p);
   SemiRegion s;
   s.up = general_bytes(p);
   s.ut = s.up + align256(3 * (size_t)r * g.Vp * e);
@@ -159,7 +162,7 @@ int glasma_layout(const glasma_params* p, size_t* bytes) {
   if (!bytes) return fail(nullptr, GLASMA_E_ARG, "bytes is NULL");
   Geom g = geom_of(p);
   const size_t e = elem(p);
-  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  const int ng = p->nc * p->nc - 1, r = stored_width(p);
   bytes[0] = 3 * (size_t)r * g.Vp * e;
   bytes[1] = bytes[0];
   bytes[2] = 3 * (size_t)ng * g.Vp * e;
@@ -185,6 +188,7 @@ int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream,
   c->g = geom_of(p);
   c->ng = p->nc * p->nc - 1;
   c->r = p->nc == 2 ? 4 : 18;
+  c->rs = stored_width(p);
   c->step = 0;
   c->cur = 0;
   c->offA = c->offB = 0;
@@ -215,13 +219,16 @@ int glasma_get_step(const glasma_ctx* ctx, int64_t* step) {
 }
 
 // Host SoA [dir][comp][V] (double) <-> device tiled records (type T), see lattice.h.
+// Links: the host array holds host_width reals per link (18 for SU(3)), the device the
+// first `width` of them (rows 0 and 1); the third row is rebuilt on load.
 template <typename T>
-static int upload(glasma_ctx* c, void* dst, const double* src, int ndir, int width) {
+static int upload(glasma_ctx* c, void* dst, const double* src, int ndir, int width, int host_width = 0) {
   const int64_t V = c->g.V, Vp = c->g.Vp;
+  if (host_width == 0) host_width = width;
   std::vector<T> tmp((size_t)ndir * width * Vp, T(0));
   for (int d = 0; d < ndir; ++d)
     for (int k = 0; k < width; ++k) {
-      const double* sp = src + ((int64_t)d * width + k) * V;
+      const double* sp = src + ((int64_t)d * host_width + k) * V;
       T* dp = tmp.data() + (int64_t)d * width * Vp;
       for (int64_t s = 0; s < V; ++s) dp[rec_elem<T>(s, k, width)] = (T)sp[s];
     }
@@ -237,7 +244,7 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
   const size_t V = c->g.V;
   int rc = dispatch(c, [&]<typename G, typename T>() -> int {
     int r;
-    if ((r = upload<T>(c, c->b.U, U, 3, c->r))) return r;
+    if ((r = upload<T>(c, c->b.U, U, 3, c->rs, c->r))) return r;
     if ((r = upload<T>(c, c->b.E, E, 3, c->ng))) return r;
     if ((r = upload<T>(c, c->b.rhoA, rhoA, 1, c->ng))) return r;
     if ((r = upload<T>(c, c->b.rhoB, rhoB, 1, c->ng))) return r;
@@ -319,7 +326,7 @@ static int semi_step(glasma_ctx* c, const StepConst& sc) {
       if (h[0] <= c->p.tol * (h[1] > 0 ? h[1] : 1e-300)) { ok = true; break; }
     }
     if (!ok) return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");
-    const int64_t nl = 3 * (int64_t)c->r * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
+    const int64_t nl = 3 * (int64_t)c->rs * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
     if (in != Un) launch_copy<G, T>(in, Un, nl, c->stream);
     launch_copy<G, T>(Et, (T*)c->b.E, ne, c->stream);
     return GLASMA_OK;
@@ -425,21 +432,38 @@ int glasma_observables(glasma_ctx* c, double* tmunu_z, double* gauss_rel, double
 }
 
 // zsrc(z) gives the stored layer that holds physical layer z (co-moving charges).
+// Links (host_width 18 > width 12): the third row of each SU(3) matrix is rebuilt as
+// conj(row 0 x row 1), as the kernels do on load.
 template <typename T, typename F>
-static int download(glasma_ctx* c, double* dst, const void* src, int ndir, int width, F zsrc) {
+static int download(glasma_ctx* c, double* dst, const void* src, int ndir, int width, F zsrc, int host_width = 0) {
   const int64_t V = c->g.V, Vp = c->g.Vp, layer = c->g.layer;
+  if (host_width == 0) host_width = width;
   std::vector<T> tmp((size_t)ndir * width * Vp);
   HIPCHK(c, hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int d = 0; d < ndir; ++d)
+  for (int d = 0; d < ndir; ++d) {
     for (int k = 0; k < width; ++k) {
-      double* dp = dst + ((int64_t)d * width + k) * V;
+      double* dp = dst + ((int64_t)d * host_width + k) * V;
       const T* sp = tmp.data() + (int64_t)d * width * Vp;
       for (int z = 0; z < c->g.nz; ++z) {
         const int64_t zs = zsrc(z);
         for (int64_t t = 0; t < layer; ++t) dp[z * layer + t] = (double)sp[rec_elem<T>(zs * layer + t, k, width)];
       }
     }
+    if (host_width == 18 && width == SU3_STORED) {
+      double* base = dst + (int64_t)d * host_width * V;
+      auto at = [&](int r, int k, int im) { return base[(2 * (3 * r + k) + im) * V]; };
+      for (int64_t s = 0; s < V; ++s, ++base) {
+        for (int k = 0; k < 3; ++k) {
+          const int a = (k + 1) % 3, b = (k + 2) % 3;
+          const double cr = at(0, a, 0) * at(1, b, 0) - at(0, a, 1) * at(1, b, 1) - (at(0, b, 0) * at(1, a, 0) - at(0, b, 1) * at(1, a, 1));
+          const double ci = at(0, a, 0) * at(1, b, 1) + at(0, a, 1) * at(1, b, 0) - (at(0, b, 0) * at(1, a, 1) + at(0, b, 1) * at(1, a, 0));
+          base[(2 * (6 + k)) * V] = cr;
+          base[(2 * (6 + k) + 1) * V] = -ci;
+        }
+      }
+    }
+  }
   return GLASMA_OK;
 }
 
@@ -451,7 +475,7 @@ int glasma_get_state(glasma_ctx* c, double* U, double* E, double* rhoA, double* 
     int r;
     auto same = [](int z) { return z; };
     const int oA = c->offA, oB = c->offB;
-    if (U && (r = download<T>(c, U, cur_U<T>(c), 3, c->r, same))) return r;
+    if (U && (r = download<T>(c, U, cur_U<T>(c), 3, c->rs, same, c->r))) return r;
     if (E && (r = download<T>(c, E, c->b.E, 3, c->ng, same))) return r;
     if (rhoA && (r = download<T>(c, rhoA, c->b.rhoA, 1, c->ng, [&](int z) { return slotA(z, oA, nz); }))) return r;
     if (rhoB && (r = download<T>(c, rhoB, c->b.rhoB, 1, c->ng, [&](int z) { return slotB(z, oB, nz); }))) return r;
@@ -833,7 +857,7 @@ struct AdjRegion {
 static AdjRegion adj_region(const glasma_params* p, int32_t steps, int32_t every) {
   Geom g = geom_of(p);
   const size_t e = elem(p);
-  const int ng = p->nc * p->nc - 1, r = p->nc == 2 ? 4 : 18;
+  const int ng = p->nc * p->nc - 1, r = stored_width(p);
   AdjRegion a;
   a.sU = align256(3 * (size_t)r * g.Vp * e);
   a.sE = align256(3 * (size_t)ng * g.Vp * e);
@@ -873,7 +897,7 @@ static int off_at(const glasma_ctx* c, int64_t s0, int off0, int64_t s) {
 
 static int save_state(glasma_ctx* c, const AdjRegion& a, StatePtr d) {
   const size_t e = elem(&c->p);
-  HIPCHK(c, hipMemcpyAsync(d.U, c->cur ? c->b.U_alt : c->b.U, 3 * (size_t)c->r * c->g.Vp * e,
+  HIPCHK(c, hipMemcpyAsync(d.U, c->cur ? c->b.U_alt : c->b.U, 3 * (size_t)c->rs * c->g.Vp * e,
                            hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(d.E, c->b.E, 3 * (size_t)c->ng * c->g.Vp * e, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(d.rA, c->b.rhoA, (size_t)c->ng * c->g.Vp * e, hipMemcpyDeviceToDevice, c->stream));
@@ -1026,7 +1050,7 @@ int glasma_set_state_device(glasma_ctx* c, const double* U, const double* E, con
   if (!c || !U || !E || !rhoA || !rhoB) return fail(c, GLASMA_E_ARG, "NULL argument");
   if (step0 < 0) return fail(c, GLASMA_E_ARG, "step0 must be >= 0");
   dispatch(c, [&]<typename G, typename T>() -> int {
-    launch_pack<G, T>(U, nullptr, (T*)c->b.U, c->g, 3, c->r, c->stream);
+    launch_pack_links<G, T>(U, (T*)c->b.U, c->g, c->stream);
     launch_pack<G, T>(E, nullptr, (T*)c->b.E, c->g, 3, c->ng, c->stream);
     launch_pack<G, T>(rhoA, ampA, (T*)c->b.rhoA, c->g, 1, c->ng, c->stream);
     launch_pack<G, T>(rhoB, ampB, (T*)c->b.rhoB, c->g, 1, c->ng, c->stream);
@@ -1045,7 +1069,7 @@ int glasma_get_state_device(glasma_ctx* c, double* U, double* E, double* rhoA, d
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
   dispatch(c, [&]<typename G, typename T>() -> int {
-    if (U) launch_unpack<G, T>(cur_U<T>(c), U, c->g, 3, c->r, 0, 0, c->stream);
+    if (U) launch_unpack_links<G, T>(cur_U<T>(c), U, c->g, c->stream);
     if (E) launch_unpack<G, T>((const T*)c->b.E, E, c->g, 3, c->ng, 0, 0, c->stream);
     if (rhoA) launch_unpack<G, T>((const T*)c->b.rhoA, rhoA, c->g, 1, c->ng, c->offA, 1, c->stream);
     if (rhoB) launch_unpack<G, T>((const T*)c->b.rhoB, rhoB, c->g, 1, c->ng, c->offB, 2, c->stream);

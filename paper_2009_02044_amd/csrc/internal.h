@@ -99,6 +99,10 @@ void launch_pack(const double* src, const double* amp, S* dst, const Geom& g, in
 template <typename G, typename S>
 void launch_unpack(const S* src, double* dst, const Geom& g, int ndir, int width, int off, int kind, hipStream_t st);
 template <typename G, typename S>
+void launch_pack_links(const double* src, S* dst, const Geom& g, hipStream_t st);
+template <typename G, typename S>
+void launch_unpack_links(const S* src, double* dst, const Geom& g, hipStream_t st);
+template <typename G, typename S>
 void launch_amp(const double* rbar, const double* base, const S* rho, int off, int which, const Geom& g, double* out,
                 hipStream_t st);
 

@@ -6,8 +6,8 @@
 // of 64 chunks per group (see the record access below), so every lane fetches a
 // link or an algebra element with few 16-byte loads and a wavefront's load covers a
 // contiguous 1 KiB.
-//   links  direction i: width R (SU(2): 4 quaternion reals; SU(3): 18 reals,
-//          c = 2 (3 r + k) + {0 re, 1 im})
+//   links  direction i: SU(2): 4 quaternion reals; SU(3): rows 0 and 1, 12 reals,
+//          c = 2 (3 r + k) + {0 re, 1 im} (row 2 is rebuilt on load, see load_link)
 //   E      direction i: width NG (algebra components E^a = 2 Tr(t^a E))
 //   rho    width NG
 // The site count is padded to Vp (a multiple of 64) and direction i of a field
@@ -136,30 +136,46 @@ template <typename T, typename S>
 GL_HD void store_link(const Q2<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
   store_comps<T, S, 4>(l.q, field_dir(U, i, 4, Vp), s);
 }
+// SU(3) links are stored by their first two rows (12 reals, c = 2 (3 r + k) + {re, im},
+// r = 0, 1); for a special unitary matrix the third row is conj(row 0 x row 1), rebuilt on
+// every load.  A third fewer bytes and load instructions than the full matrix.
+constexpr int SU3_STORED = 12;
 template <typename T, typename S>
 GL_HD void load_link(M3<T>& l, const S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  T v[18];
-  load_comps<T, S, 18>(v, field_dir(U, i, 18, Vp), s);
+  T v[SU3_STORED];
+  load_comps<T, S, SU3_STORED>(v, field_dir(U, i, SU3_STORED, Vp), s);
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       l.re[r][k] = v[2 * (3 * r + k)];
       l.im[r][k] = v[2 * (3 * r + k) + 1];
     }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const T cr = l.re[0][a] * l.re[1][b] - l.im[0][a] * l.im[1][b] - (l.re[0][b] * l.re[1][a] - l.im[0][b] * l.im[1][a]);
+    const T ci = l.re[0][a] * l.im[1][b] + l.im[0][a] * l.re[1][b] - (l.re[0][b] * l.im[1][a] + l.im[0][b] * l.re[1][a]);
+    l.re[2][k] = cr;
+    l.im[2][k] = -ci;
+  }
 }
 template <typename T, typename S>
 GL_HD void store_link(const M3<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
-  T v[18];
+  T v[SU3_STORED];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       v[2 * (3 * r + k)] = l.re[r][k];
       v[2 * (3 * r + k) + 1] = l.im[r][k];
     }
-  store_comps<T, S, 18>(v, field_dir(U, i, 18, Vp), s);
+  store_comps<T, S, SU3_STORED>(v, field_dir(U, i, SU3_STORED, Vp), s);
 }
+// stored reals per link
+template <typename L> struct StoredWidth;
+template <typename T> struct StoredWidth<Q2<T>> { static constexpr int value = 4; };
+template <typename T> struct StoredWidth<M3<T>> { static constexpr int value = SU3_STORED; };
 
 // ---- algebra load / store: f = field base, i = direction (0 for rho) ----------
 template <typename A, typename S>

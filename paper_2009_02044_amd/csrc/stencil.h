@@ -4,6 +4,17 @@
 
 namespace gl {
 
+// Optional scheduling fence between staples (limits how many links the compiler keeps
+// in flight at once; a register-pressure / occupancy trade-off, off by default).
+#ifndef GL_STAPLE_FENCE
+#define GL_STAPLE_FENCE 0
+#endif
+__device__ __forceinline__ void staple_fence() {
+#if GL_STAPLE_FENCE
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // S = sum_{j != i} a_j^-2 [ U_j(x+i) U_i^dag(x+j) U_j^dag(x) + U_j^dag(x+i-j) U_i^dag(x-j) U_j(x-j) ]
 // so that U_i(x) S = sum_{j != i} a_j^-2 (U_{i,j}(x) + U_{i,-j}(x)).  G is the group in
 // the compute precision; the links are read from storage of type T.
@@ -27,10 +38,12 @@ __device__ __forceinline__ typename G::Link staple_sum(const T* __restrict__ U, 
     load_link(B, U, i, idx(g, xpj), Vp);
     load_link(C, U, j, idx(g, x), Vp);
     G::add_to(S, G::mul_dag(G::mul_dag(A, B), C), w);
+    staple_fence();
     load_link(A, U, j, idx(g, xpimj), Vp);
     load_link(B, U, i, idx(g, xmj), Vp);
     load_link(C, U, j, idx(g, xmj), Vp);
     G::add_to(S, G::dag_mul(G::mul(B, A), C), w);
+    staple_fence();
   }
   return S;
 }

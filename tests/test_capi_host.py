@@ -35,7 +35,8 @@ def test_layout_sizes_and_argument_errors():
     sizes = (C.c_size_t * 6)()
     assert L.lib.glasma_layout(C.byref(p), sizes) == 0
     V = 16 * 8 * 8
-    assert sizes[0] == 3 * 18 * V * 8 and sizes[1] == sizes[0]       # V = 1024 is a multiple of 64
+    # SU(3) links are stored by rows 0 and 1 (12 reals); V = 1024 is a multiple of 64
+    assert sizes[0] == 3 * 12 * V * 8 and sizes[1] == sizes[0]
     assert sizes[2] == 3 * 8 * V * 8 and sizes[3] == 8 * V * 8 == sizes[4]
     p32 = L.Params(2, 16, 8, 4.0, 1.0, 0.5, 32, 0, 0, 50, 0.0)
     assert L.lib.glasma_layout(C.byref(p32), sizes) == 0
