@@ -24,6 +24,10 @@ template <typename T> struct Q2 { T q[4]; };                 // SU(2) span eleme
 template <typename T> struct M3 { T re[3][3]; T im[3][3]; };  // 3x3 complex
 
 template <typename T> GL_HD T sqr(T x) { return x * x; }
+// a * b + c with one rounding (v_fma_f64 / v_fma_f32); products below are written as
+// chains of these so that every term costs one instruction
+GL_HD double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+GL_HD float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename T> GL_HD void sincos_r(T x, T* s, T* c);
 template <> GL_HD void sincos_r<double>(double x, double* s, double* c) { sincos(x, s, c); }
 template <> GL_HD void sincos_r<float>(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -54,6 +58,9 @@ template <typename T> struct Su2 {
   static GL_HD Link mul_dag(const Link& a, const Link& b) { return mul(a, dag(b)); }   // a b^dag
   static GL_HD Link dag_mul(const Link& a, const Link& b) { return mul(dag(a), b); }   // a^dag b
   static GL_HD void add_to(Link& acc, const Link& a, T s) { for (int k = 0; k < 4; ++k) acc.q[k] += s * a.q[k]; }
+  static GL_HD void acc_mul_dag(Link& r, const Link& a, const Link& b) { add_to(r, mul_dag(a, b), T(1)); }
+  static GL_HD void acc_dag_mul(Link& r, const Link& a, const Link& b) { add_to(r, dag_mul(a, b), T(1)); }
+  static GL_HD void scale(Link& r, T s) { for (int k = 0; k < 4; ++k) r.q[k] *= s; }
   // (U - U^dag)/(2i) = q.s  ->  components 2 q_a
   static GL_HD Alg proj(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
   static GL_HD T retr(const Link& m) { return 2 * m.q[0]; }               // Re Tr
@@ -65,6 +72,8 @@ template <typename T> struct Su2 {
     r.c[2] = 2 * (a.q[0] * b.q[3] + b.q[0] * a.q[3] - (a.q[1] * b.q[2] - a.q[2] * b.q[1]));
     return r;
   }
+  // proj(a b^dag)
+  static GL_HD Alg proj_mul_dag(const Link& a, const Link& b) { return proj_mul(a, dag(b)); }
   // exp(i s X), X = x.s/2: cos(|sx|/2) + i sin(|sx|/2) n.s
   static GL_HD Link expi(const Alg& x, T s) {
     T v0 = s * x.c[0], v1 = s * x.c[1], v2 = s * x.c[2];
@@ -79,6 +88,8 @@ template <typename T> struct Su2 {
     Link r; r.q[0] = cs; r.q[1] = f * v0; r.q[2] = f * v1; r.q[3] = f * v2;
     return r;
   }
+  template <bool TOP = false>
+  static GL_HD Link expi_mul(const Alg& x, T s, const Link& u) { return mul(expi(x, s), u); }
   // pure quaternion i X = (0, x/2)
   static GL_HD Link alg_as_link(const Alg& x) { Link r; r.q[0] = 0; r.q[1] = x.c[0] / 2; r.q[2] = x.c[1] / 2; r.q[3] = x.c[2] / 2; return r; }
   static GL_HD Alg link_as_alg(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
@@ -131,58 +142,93 @@ template <typename T> struct Su3 {
   static GL_HD Link one() { Link r = zero(); r.re[0][0] = r.re[1][1] = r.re[2][2] = T(1); return r; }
   static GL_HD Alg alg_zero() { Alg r; for (int k = 0; k < 8; ++k) r.c[k] = T(0); return r; }
 
+  // Products of 3x3 complex matrices, each entry one chain of fused multiply-adds.
+  // re/im of the k-th term: (x y)  -> xr yr - xi yi, xr yi + xi yr
+  //                          (x y*) -> xr yr + xi yi, xi yr - xr yi
+  //                          (x* y) -> xr yr + xi yi, xr yi - xi yr
   static GL_HD Link mul(const Link& a, const Link& b) {
     Link r;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        T sr = a.re[i][0] * b.re[0][j] - a.im[i][0] * b.im[0][j];
-        T si = a.re[i][0] * b.im[0][j] + a.im[i][0] * b.re[0][j];
+        T sr = a.re[i][0] * b.re[0][j], si = a.re[i][0] * b.im[0][j];
+        sr = fmx(-a.im[i][0], b.im[0][j], sr);
+        si = fmx(a.im[i][0], b.re[0][j], si);
 #pragma unroll
         for (int k = 1; k < 3; ++k) {
-          sr += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
-          si += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+          sr = fmx(a.re[i][k], b.re[k][j], sr);
+          sr = fmx(-a.im[i][k], b.im[k][j], sr);
+          si = fmx(a.re[i][k], b.im[k][j], si);
+          si = fmx(a.im[i][k], b.re[k][j], si);
         }
         r.re[i][j] = sr; r.im[i][j] = si;
       }
     return r;
   }
-  // a b^dag: (a b^dag)_ij = sum_k a_ik conj(b_jk)
-  static GL_HD Link mul_dag(const Link& a, const Link& b) {
-    Link r;
+  // r (+)= a b^dag: (a b^dag)_ij = sum_k a_ik conj(b_jk)
+  template <bool ACC>
+  static GL_HD void mul_dag_into(Link& r, const Link& a, const Link& b) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        T sr = a.re[i][0] * b.re[j][0] + a.im[i][0] * b.im[j][0];
-        T si = a.im[i][0] * b.re[j][0] - a.re[i][0] * b.im[j][0];
+        T sr, si;
+        if (ACC) {
+          sr = fmx(a.re[i][0], b.re[j][0], r.re[i][j]);
+          si = fmx(a.im[i][0], b.re[j][0], r.im[i][j]);
+        } else {
+          sr = a.re[i][0] * b.re[j][0];
+          si = a.im[i][0] * b.re[j][0];
+        }
+        sr = fmx(a.im[i][0], b.im[j][0], sr);
+        si = fmx(-a.re[i][0], b.im[j][0], si);
 #pragma unroll
         for (int k = 1; k < 3; ++k) {
-          sr += a.re[i][k] * b.re[j][k] + a.im[i][k] * b.im[j][k];
-          si += a.im[i][k] * b.re[j][k] - a.re[i][k] * b.im[j][k];
+          sr = fmx(a.re[i][k], b.re[j][k], sr);
+          sr = fmx(a.im[i][k], b.im[j][k], sr);
+          si = fmx(a.im[i][k], b.re[j][k], si);
+          si = fmx(-a.re[i][k], b.im[j][k], si);
         }
         r.re[i][j] = sr; r.im[i][j] = si;
       }
-    return r;
   }
-  // a^dag b: sum_k conj(a_ki) b_kj
-  static GL_HD Link dag_mul(const Link& a, const Link& b) {
-    Link r;
+  // r (+)= a^dag b: (a^dag b)_ij = sum_k conj(a_ki) b_kj
+  template <bool ACC>
+  static GL_HD void dag_mul_into(Link& r, const Link& a, const Link& b) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        T sr = a.re[0][i] * b.re[0][j] + a.im[0][i] * b.im[0][j];
-        T si = a.re[0][i] * b.im[0][j] - a.im[0][i] * b.re[0][j];
+        T sr, si;
+        if (ACC) {
+          sr = fmx(a.re[0][i], b.re[0][j], r.re[i][j]);
+          si = fmx(a.re[0][i], b.im[0][j], r.im[i][j]);
+        } else {
+          sr = a.re[0][i] * b.re[0][j];
+          si = a.re[0][i] * b.im[0][j];
+        }
+        sr = fmx(a.im[0][i], b.im[0][j], sr);
+        si = fmx(-a.im[0][i], b.re[0][j], si);
 #pragma unroll
         for (int k = 1; k < 3; ++k) {
-          sr += a.re[k][i] * b.re[k][j] + a.im[k][i] * b.im[k][j];
-          si += a.re[k][i] * b.im[k][j] - a.im[k][i] * b.re[k][j];
+          sr = fmx(a.re[k][i], b.re[k][j], sr);
+          sr = fmx(a.im[k][i], b.im[k][j], sr);
+          si = fmx(a.re[k][i], b.im[k][j], si);
+          si = fmx(-a.im[k][i], b.re[k][j], si);
         }
         r.re[i][j] = sr; r.im[i][j] = si;
       }
-    return r;
+  }
+  static GL_HD Link mul_dag(const Link& a, const Link& b) { Link r; mul_dag_into<false>(r, a, b); return r; }
+  static GL_HD Link dag_mul(const Link& a, const Link& b) { Link r; dag_mul_into<false>(r, a, b); return r; }
+  static GL_HD void acc_mul_dag(Link& r, const Link& a, const Link& b) { mul_dag_into<true>(r, a, b); }
+  static GL_HD void acc_dag_mul(Link& r, const Link& a, const Link& b) { dag_mul_into<true>(r, a, b); }
+  static GL_HD void scale(Link& r, T s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { r.re[i][j] *= s; r.im[i][j] *= s; }
   }
   static GL_HD Link dag(const Link& a) {
     Link r;
@@ -213,33 +259,67 @@ template <typename T> struct Su3 {
     return r;
   }
   static GL_HD T retr(const Link& m) { return m.re[0][0] + m.re[1][1] + m.re[2][2]; }
-  // proj(a b) from the six off-diagonal entries and the imaginary diagonal of a b
-  static GL_HD Alg proj_mul(const Link& a, const Link& b) {
-    T mr[3][3], mi[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        T sr = T(0), si = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if (i != j) sr += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
-          si += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
-        }
-        mr[i][j] = sr; mi[i][j] = si;
-      }
+  // proj(M) of a product M = a b or a b^dag without forming M: each off-diagonal
+  // component is one fused chain over the two entries it combines, and only the
+  // imaginary diagonal of M is formed (its real part drops out).
+  // DAG selects b^dag: B(k, j) = b_kj, or conj(b_jk).
+  template <bool DAG>
+  static GL_HD void bent(const Link& b, int k, int j, T& r, T& i) {
+    if (DAG) { r = b.re[j][k]; i = -b.im[j][k]; } else { r = b.re[k][j]; i = b.im[k][j]; }
+  }
+  template <bool DAG>
+  static GL_HD Alg proj_prod(const Link& a, const Link& b) {
     const T is3 = T(0.57735026918962576451);
+    // Im M_pq + Im M_qp and Re M_pq - Re M_qp for the pairs (0,1), (0,2), (1,2)
+    T sym[3], asym[3];
+    const int P[3] = {0, 0, 1}, Qd[3] = {1, 2, 2};
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int p = P[n], q = Qd[n];
+      T y = T(0), z = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T bkq_r, bkq_i, bkp_r, bkp_i;
+        bent<DAG>(b, k, q, bkq_r, bkq_i);
+        bent<DAG>(b, k, p, bkp_r, bkp_i);
+        // M_pq = sum_k a_pk B_kq, M_qp = sum_k a_qk B_kp
+        y = fmx(a.re[p][k], bkq_i, y);
+        y = fmx(a.im[p][k], bkq_r, y);
+        y = fmx(a.re[q][k], bkp_i, y);
+        y = fmx(a.im[q][k], bkp_r, y);
+        z = fmx(a.re[p][k], bkq_r, z);
+        z = fmx(-a.im[p][k], bkq_i, z);
+        z = fmx(-a.re[q][k], bkp_r, z);
+        z = fmx(a.im[q][k], bkp_i, z);
+      }
+      sym[n] = y; asym[n] = z;
+    }
+    T di[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      T y = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T r, i;
+        bent<DAG>(b, k, p, r, i);
+        y = fmx(a.re[p][k], i, y);
+        y = fmx(a.im[p][k], r, y);
+      }
+      di[p] = y;
+    }
     Alg r;
-    r.c[0] = mi[0][1] + mi[1][0];
-    r.c[1] = mr[0][1] - mr[1][0];
-    r.c[2] = mi[0][0] - mi[1][1];
-    r.c[3] = mi[0][2] + mi[2][0];
-    r.c[4] = mr[0][2] - mr[2][0];
-    r.c[5] = mi[1][2] + mi[2][1];
-    r.c[6] = mr[1][2] - mr[2][1];
-    r.c[7] = (mi[0][0] + mi[1][1] - T(2) * mi[2][2]) * is3;
+    r.c[0] = sym[0];
+    r.c[1] = asym[0];
+    r.c[2] = di[0] - di[1];
+    r.c[3] = sym[1];
+    r.c[4] = asym[1];
+    r.c[5] = sym[2];
+    r.c[6] = asym[2];
+    r.c[7] = (di[0] + di[1] - T(2) * di[2]) * is3;
     return r;
   }
+  static GL_HD Alg proj_mul(const Link& a, const Link& b) { return proj_prod<false>(a, b); }
+  static GL_HD Alg proj_mul_dag(const Link& a, const Link& b) { return proj_prod<true>(a, b); }
   // hermitian matrix X = sum_a x^a lambda^a / 2, scaled by s
   static GL_HD Link herm(const Alg& x, T s) {
     const T is3 = T(0.57735026918962576451);
@@ -274,43 +354,56 @@ template <typename T> struct Su3 {
     return r;
   }
 
-  // Q^2 for hermitian Q (the result is hermitian: upper triangle computed, lower mirrored)
-  static GL_HD Link herm_sq(const Link& Q) {
-    Link r;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = i; j < 3; ++j) {
-        T sr = T(0), si = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          sr += Q.re[i][k] * Q.re[k][j] - Q.im[i][k] * Q.im[k][j];
-          si += Q.re[i][k] * Q.im[k][j] + Q.im[i][k] * Q.re[k][j];
-        }
-        r.re[i][j] = sr; r.im[i][j] = (i == j) ? T(0) : si;
-        if (j != i) { r.re[j][i] = sr; r.im[j][i] = -si; }
-      }
-    return r;
+  // A hermitian 3x3 matrix by its real diagonal d and the entries (0,1), (0,2), (1,2)
+  // above it (real parts r, imaginary parts i); the entries below are their conjugates.
+  struct Herm { T d[3], r[3], i[3]; };
+  // Q = s x^a t^a
+  static GL_HD Herm herm_c(const Alg& x, T s) {
+    const T is3 = T(0.57735026918962576451);
+    const T h = s * T(0.5);
+    const T t7 = h * is3 * x.c[7], t2 = h * x.c[2];
+    Herm q;
+    q.d[0] = t7 + t2; q.d[1] = t7 - t2; q.d[2] = T(-2) * t7;
+    q.r[0] = h * x.c[0]; q.i[0] = -h * x.c[1];
+    q.r[1] = h * x.c[3]; q.i[1] = -h * x.c[4];
+    q.r[2] = h * x.c[5]; q.i[2] = -h * x.c[6];
+    return q;
   }
 
   // exp(i Q) for Q = s x^a t^a hermitian traceless.  By Cayley-Hamilton every power of
-  // Q is a combination of 1, Q, Q^2 (Q^3 = c1 Q + c0 with c0 = det Q = Tr Q^3 / 3,
-  // c1 = Tr Q^2 / 2), so exp(iQ) = h0 + h1 Q + h2 Q^2 with complex scalars h.  They
-  // are obtained by scaling and squaring in that coefficient space: the exponential
-  // series of Q / 2^k (spectral radius <= 1/2, sqrt(4 c1 / 3) bounds it) is summed to
-  // a remainder below the unit roundoff (14 terms in double, 8 in float), and each of
-  // the k squarings (h0 + h1 Q + h2 Q^2)^2 is reduced with the same identity.  Exact
-  // to rounding; no transcendental functions and no branches on the data apart from k.
+  // Q is a combination of 1, Q, Q^2 (Q^3 = c1 Q + c0 with c0 = det Q, c1 = Tr Q^2 / 2),
+  // so exp(iQ) = h0 + h1 Q + h2 Q^2 with complex scalars h.  They are obtained by
+  // scaling and squaring in that coefficient space: the exponential series of Q / 2^k
+  // (spectral radius <= 1/2, sqrt(4 c1 / 3) bounds it) is summed to a remainder below
+  // the unit roundoff (14 terms in double, 8 in float), and each of the k squarings
+  // (h0 + h1 Q + h2 Q^2)^2 is reduced with the same identity.  Exact to rounding; no
+  // transcendental functions and no branches on the data apart from k.  Returns
+  // exp(iQ) as a matrix (hermitian structure of Q and Q^2 used throughout).
   static GL_HD Link expi(const Alg& x, T s) {
-    Link Q = herm(x, s);
-    Link Q2 = herm_sq(Q);
-    const T c1 = T(0.5) * (Q2.re[0][0] + Q2.re[1][1] + Q2.re[2][2]);
-    T trq3 = T(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) trq3 += Q.re[i][k] * Q2.re[k][i] - Q.im[i][k] * Q2.im[k][i];
-    const T c0 = trq3 / T(3);
+    const Herm q = herm_c(x, s);
+    // P = Q^2
+    const T n0 = fmx(q.r[0], q.r[0], q.i[0] * q.i[0]);
+    const T n1 = fmx(q.r[1], q.r[1], q.i[1] * q.i[1]);
+    const T n2 = fmx(q.r[2], q.r[2], q.i[2] * q.i[2]);
+    Herm p;
+    p.d[0] = fmx(q.d[0], q.d[0], n0 + n1);
+    p.d[1] = fmx(q.d[1], q.d[1], n0 + n2);
+    p.d[2] = fmx(q.d[2], q.d[2], n1 + n2);
+    const T s01 = q.d[0] + q.d[1], s02 = q.d[0] + q.d[2], s12 = q.d[1] + q.d[2];
+    p.r[0] = fmx(q.r[0], s01, fmx(q.r[1], q.r[2], q.i[1] * q.i[2]));
+    p.i[0] = fmx(q.i[0], s01, fmx(q.i[1], q.r[2], -q.r[1] * q.i[2]));
+    p.r[1] = fmx(q.r[1], s02, fmx(q.r[0], q.r[2], -q.i[0] * q.i[2]));
+    p.i[1] = fmx(q.i[1], s02, fmx(q.r[0], q.i[2], q.i[0] * q.r[2]));
+    p.r[2] = fmx(q.r[2], s12, fmx(q.r[0], q.r[1], q.i[0] * q.i[1]));
+    p.i[2] = fmx(q.i[2], s12, fmx(q.r[0], q.i[1], -q.i[0] * q.r[1]));
+    const T c1 = T(0.5) * (p.d[0] + p.d[1] + p.d[2]);
+    // c0 = det Q = d0 d1 d2 - d0 |q12|^2 - d1 |q02|^2 - d2 |q01|^2 + 2 Re(q01 q12 conj(q02))
+    const T acr = fmx(q.r[0], q.r[2], -q.i[0] * q.i[2]), aci = fmx(q.r[0], q.i[2], q.i[0] * q.r[2]);
+    T c0 = q.d[0] * q.d[1] * q.d[2];
+    c0 = fmx(-q.d[0], n2, c0);
+    c0 = fmx(-q.d[1], n1, c0);
+    c0 = fmx(-q.d[2], n0, c0);
+    c0 = fmx(T(2), fmx(acr, q.r[1], aci * q.i[1]), c0);
     // scaling: k halvings bring the spectral radius bound below 1/2
     T r2 = T(4) / T(3) * c1;       // bound on the squared spectral radius
     int k = 0;
@@ -324,18 +417,17 @@ template <typename T> struct Su3 {
     T w = T(1);
 #pragma unroll
     for (int n = 1; n <= NT; ++n) {
-      const T an = c0k * c, bn = a + c1k * c, cn = b;
+      const T an = c0k * c, bn = fmx(c1k, c, a), cn = b;
       a = an; b = bn; c = cn;
       w /= T(n);
       // i^n: 1, i, -1, -i
-      if ((n & 3) == 0) { g0r += w * a; g1r += w * b; g2r += w * c; }
-      else if ((n & 3) == 1) { g0i += w * a; g1i += w * b; g2i += w * c; }
-      else if ((n & 3) == 2) { g0r -= w * a; g1r -= w * b; g2r -= w * c; }
-      else { g0i -= w * a; g1i -= w * b; g2i -= w * c; }
+      const T ws = ((n & 3) < 2) ? w : -w;
+      if (n & 1) { g0i = fmx(ws, a, g0i); g1i = fmx(ws, b, g1i); g2i = fmx(ws, c, g2i); }
+      else { g0r = fmx(ws, a, g0r); g1r = fmx(ws, b, g1r); g2r = fmx(ws, c, g2r); }
     }
     // coefficients with respect to Q
     T h0r = g0r, h0i = g0i, h1r = g1r * sc, h1i = g1i * sc, h2r = g2r * sc * sc, h2i = g2i * sc * sc;
-    for (int q = 0; q < k; ++q) {
+    for (int m = 0; m < k; ++m) {
       // n0 = h0^2 + 2 h1 h2 c0, n1 = 2 h0 h1 + 2 h1 h2 c1 + h2^2 c0, n2 = h1^2 + 2 h0 h2 + h2^2 c1
       const T h00r = h0r * h0r - h0i * h0i, h00i = T(2) * h0r * h0i;
       const T h12r = h1r * h2r - h1i * h2i, h12i = h1r * h2i + h1i * h2r;
@@ -347,18 +439,52 @@ template <typename T> struct Su3 {
       h1r = T(2) * h01r + T(2) * c1 * h12r + c0 * h22r; h1i = T(2) * h01i + T(2) * c1 * h12i + c0 * h22i;
       h2r = h11r + T(2) * h02r + c1 * h22r; h2i = h11i + T(2) * h02i + c1 * h22i;
     }
+    // R = h0 + h1 Q + h2 Q^2
     Link R;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) {
+      R.re[d][d] = fmx(h1r, q.d[d], fmx(h2r, p.d[d], h0r));
+      R.im[d][d] = fmx(h1i, q.d[d], fmx(h2i, p.d[d], h0i));
+    }
+    const int UP[3] = {0, 0, 1}, LO[3] = {1, 2, 2};
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const T A = fmx(h1r, q.r[n], h2r * p.r[n]);
+      const T B = fmx(h1i, q.i[n], h2i * p.i[n]);
+      const T C = fmx(h1r, q.i[n], h2r * p.i[n]);
+      const T D = fmx(h1i, q.r[n], h2i * p.r[n]);
+      R.re[UP[n]][LO[n]] = A - B; R.im[UP[n]][LO[n]] = C + D;
+      R.re[LO[n]][UP[n]] = A + B; R.im[LO[n]][UP[n]] = D - C;
+    }
+    return R;
+  }
+  // exp(i s X) u; with TOP only rows 0 and 1 are formed (row 2 is set to zero), which
+  // is all that the two-row link storage keeps.
+  template <bool TOP = false>
+  static GL_HD Link expi_mul(const Alg& x, T s, const Link& u) {
+    const Link R = expi(x, s);
+    Link r;
+    constexpr int NR = TOP ? 2 : 3;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const T qr = Q.re[i][j], qi = Q.im[i][j], pr = Q2.re[i][j], pi = Q2.im[i][j];
-        R.re[i][j] = h1r * qr - h1i * qi + h2r * pr - h2i * pi;
-        R.im[i][j] = h1r * qi + h1i * qr + h2r * pi + h2i * pr;
-      }
+        T sr = R.re[i][0] * u.re[0][j], si = R.re[i][0] * u.im[0][j];
+        sr = fmx(-R.im[i][0], u.im[0][j], sr);
+        si = fmx(R.im[i][0], u.re[0][j], si);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { R.re[i][i] += h0r; R.im[i][i] += h0i; }
-    return R;
+        for (int k = 1; k < 3; ++k) {
+          sr = fmx(R.re[i][k], u.re[k][j], sr);
+          sr = fmx(-R.im[i][k], u.im[k][j], sr);
+          si = fmx(R.re[i][k], u.im[k][j], si);
+          si = fmx(R.im[i][k], u.re[k][j], si);
+        }
+        r.re[i][j] = sr; r.im[i][j] = si;
+      }
+    if (TOP)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { r.re[2][j] = T(0); r.im[2][j] = T(0); }
+    return r;
   }
   // U^dag X U
   static GL_HD Alg transport(const Link& u, const Alg& x) {

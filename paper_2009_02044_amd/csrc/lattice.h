@@ -136,6 +136,25 @@ template <typename T, typename S>
 GL_HD void store_link(const Q2<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
   store_comps<T, S, 4>(l.q, field_dir(U, i, 4, Vp), s);
 }
+// Row 2 of a special unitary matrix from rows 0 and 1: u_2k = conj(u_0a u_1b - u_0b u_1a),
+// (a, b) = (k+1, k+2) mod 3; each real part one fused chain.
+template <typename T>
+GL_HD void complete_row2(M3<T>& l) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    T cr = l.re[0][a] * l.re[1][b];
+    cr = fmx(-l.im[0][a], l.im[1][b], cr);
+    cr = fmx(-l.re[0][b], l.re[1][a], cr);
+    cr = fmx(l.im[0][b], l.im[1][a], cr);
+    T ci = l.re[0][a] * l.im[1][b];
+    ci = fmx(l.im[0][a], l.re[1][b], ci);
+    ci = fmx(-l.re[0][b], l.im[1][a], ci);
+    ci = fmx(-l.im[0][b], l.re[1][a], ci);
+    l.re[2][k] = cr;
+    l.im[2][k] = -ci;
+  }
+}
 // SU(3) links are stored by their first two rows (12 reals, c = 2 (3 r + k) + {re, im},
 // r = 0, 1); for a special unitary matrix the third row is conj(row 0 x row 1), rebuilt on
 // every load.  A third fewer bytes and load instructions than the full matrix.
@@ -151,14 +170,7 @@ GL_HD void load_link(M3<T>& l, const S* __restrict__ U, int i, uint32_t s, int64
       l.re[r][k] = v[2 * (3 * r + k)];
       l.im[r][k] = v[2 * (3 * r + k) + 1];
     }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int a = (k + 1) % 3, b = (k + 2) % 3;
-    const T cr = l.re[0][a] * l.re[1][b] - l.im[0][a] * l.im[1][b] - (l.re[0][b] * l.re[1][a] - l.im[0][b] * l.im[1][a]);
-    const T ci = l.re[0][a] * l.im[1][b] + l.im[0][a] * l.re[1][b] - (l.re[0][b] * l.im[1][a] + l.im[0][b] * l.re[1][a]);
-    l.re[2][k] = cr;
-    l.im[2][k] = -ci;
-  }
+  complete_row2(l);
 }
 template <typename T, typename S>
 GL_HD void store_link(const M3<T>& l, S* __restrict__ U, int i, uint32_t s, int64_t Vp) {

@@ -7,7 +7,7 @@ namespace gl {
 // Optional scheduling fence between staples (limits how many links the compiler keeps
 // in flight at once; a register-pressure / occupancy trade-off, off by default).
 #ifndef GL_STAPLE_FENCE
-#define GL_STAPLE_FENCE 0
+#define GL_STAPLE_FENCE 1
 #endif
 __device__ __forceinline__ void staple_fence() {
 #if GL_STAPLE_FENCE
@@ -48,52 +48,59 @@ __device__ __forceinline__ typename G::Link staple_sum(const T* __restrict__ U, 
   return S;
 }
 
-// All three staple sums at once, visiting each unordered pair {i, j} once: the product
-// P = U_j(x+i) U_i^dag(x+j) serves both forward staples, P U_j^dag(x) for direction i
-// and P^dag U_i^dag(x) for direction j, and every neighbour link is loaded once per
-// pair.  The own links arrive in Ux.
-template <typename G, typename T>
-__device__ __forceinline__ void staple_sums_pairs(const T* __restrict__ U, const Geom& g, Site x,
-                                                  const typename G::Link (&Ux)[3], const double* inv_a2,
-                                                  typename G::Link (&S)[3]) {
+// The other two directions of i in increasing order.
+GL_HD int other_lo(int i) { return i == 0 ? 1 : 0; }
+GL_HD int other_hi(int i) { return i == 2 ? 1 : 2; }
+
+// Staple sum of direction i for the step kernel.  With (j1, j2) = (other_lo(i),
+// other_hi(i)) and w_j = a_j^-2 it returns
+//   S = (w_j1 / w_j2) [fwd_j1 + bwd_j1] + [fwd_j2 + bwd_j2],
+//   fwd_j = U_j(x+i) U_i^dag(x+j) U_j^dag(x),  bwd_j = U_j^dag(x+i-j) U_i^dag(x-j) U_j(x-j),
+// so that sum_j w_j (U_{i,j} + U_{i,-j}) = w_j2 U_i(x) S.  The last product of every
+// staple accumulates into S as one fused chain per entry, and a single scaling by
+// ratio = w_j1 / w_j2 stands in for the per-staple weights.
+// Link sources for the staple sums: fetch(l, d, s) sets l = U_d at site s.
+template <typename T> struct GlobalLinks {
+  const T* __restrict__ U;
+  int64_t Vp;
+  template <typename L> __device__ __forceinline__ void operator()(L& l, int d, uint32_t s) const {
+    load_link(l, U, d, s, Vp);
+  }
+};
+
+template <typename G, typename F>
+__device__ __forceinline__ typename G::Link staple_sum_scaled_f(const F& fetch, const Geom& g, Site x, int i,
+                                                                typename G::Real ratio) {
   using L = typename G::Link;
-  using R = typename G::Real;
-  const int64_t Vp = g.Vp;
+  L S;
+  Site xpi = shifted(g, x, i, +1);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) S[i] = G::zero();
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i + 1; j < 3; ++j) {
-      const R wi = (R)inv_a2[j], wj = (R)inv_a2[i];   // weight of the (i,j) plane in F_i and F_j
-      Site xpi = shifted(g, x, i, +1), xpj = shifted(g, x, j, +1);
-      {
-        L A, B;
-        load_link(A, U, j, idx(g, xpi), Vp);
-        load_link(B, U, i, idx(g, xpj), Vp);
-        L P = G::mul_dag(A, B);                        // U_j(x+i) U_i^dag(x+j)
-        G::add_to(S[i], G::mul_dag(P, Ux[j]), wi);
-        G::add_to(S[j], G::dag_mul(P, G::dag(Ux[i])), wj);
-      }
-      {
-        // backward staple of direction i in the (i, -j) plane
-        Site xmj = shifted(g, x, j, -1);
-        L A, B, C;
-        load_link(A, U, j, idx(g, shifted(g, xpi, j, -1)), Vp);
-        load_link(B, U, i, idx(g, xmj), Vp);
-        load_link(C, U, j, idx(g, xmj), Vp);
-        G::add_to(S[i], G::dag_mul(G::mul(B, A), C), wi);
-      }
-      {
-        // backward staple of direction j in the (j, -i) plane
-        Site xmi = shifted(g, x, i, -1);
-        L A, B, C;
-        load_link(A, U, i, idx(g, shifted(g, xpj, i, -1)), Vp);
-        load_link(B, U, j, idx(g, xmi), Vp);
-        load_link(C, U, i, idx(g, xmi), Vp);
-        G::add_to(S[j], G::dag_mul(G::mul(B, A), C), wj);
-      }
-    }
+  for (int n = 0; n < 2; ++n) {
+    const int j = n == 0 ? other_lo(i) : other_hi(i);
+    Site xpj = shifted(g, x, j, +1);
+    Site xmj = shifted(g, x, j, -1);
+    Site xpimj = shifted(g, xpi, j, -1);
+    L A, B, C;
+    fetch(A, j, idx(g, xpi));
+    fetch(B, i, idx(g, xpj));
+    fetch(C, j, idx(g, x));
+    const L P = G::mul_dag(A, B);
+    if (n == 0) S = G::mul_dag(P, C);
+    else G::acc_mul_dag(S, P, C);
+    staple_fence();
+    fetch(A, j, idx(g, xpimj));
+    fetch(B, i, idx(g, xmj));
+    fetch(C, j, idx(g, xmj));
+    G::acc_dag_mul(S, G::mul(B, A), C);
+    if (n == 0) G::scale(S, ratio);
+    staple_fence();
+  }
+  return S;
+}
+template <typename G, typename T>
+__device__ __forceinline__ typename G::Link staple_sum_scaled(const T* __restrict__ U, const Geom& g, Site x,
+                                                              int i, typename G::Real ratio) {
+  return staple_sum_scaled_f<G>(GlobalLinks<T>{U, g.Vp}, g, x, i, ratio);
 }
 
 // Forward plaquette U_{i,j}(x) = U_i(x) U_j(x+i) U_i^dag(x+j) U_j^dag(x) (eq. plaquette).

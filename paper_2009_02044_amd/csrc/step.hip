@@ -20,8 +20,9 @@
 namespace gl {
 
 // Update of link (x, i): staples, E, CPIC hop (z links on hop steps), exp, new link.
-template <typename G, typename T, bool HOP>
-__device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restrict__ Unew, T* __restrict__ E,
+// fetch(l, d, s) supplies the links at time t (from the work-group's LDS tile or memory).
+template <typename G, typename T, bool HOP, typename F>
+__device__ __forceinline__ void update_link(const F& fetch, T* __restrict__ Unew, T* __restrict__ E,
                                             T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
                                             const StepConst& c, const double* inv_a2, Site x, uint32_t s, int i,
                                             bool reunit = false) {
@@ -29,13 +30,14 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
   using A = typename G::Alg;
   constexpr int NG = G::NG;
   const int64_t Vp = g.Vp;
-  L S = staple_sum<G, T>(U, g, x, i, inv_a2);
+  const double w1 = inv_a2[other_lo(i)], w2 = inv_a2[other_hi(i)];
+  L S = staple_sum_scaled_f<G>(fetch, g, x, i, (T)(w1 / w2));
   L Ui;
-  load_link(Ui, U, i, s, Vp);
+  fetch(Ui, i, s);
   A f = G::proj_mul(Ui, S);
   A e;
   load_alg(e, E, i, s, Vp);
-  const T kf = (T)(-c.dt / c.a[i]);
+  const T kf = (T)(-c.dt / c.a[i] * w2);
 #pragma unroll
   for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
   if (HOP && i == 2) {
@@ -54,7 +56,8 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
     for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
   }
   store_alg(e, E, i, s, Vp);
-  L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
+  // rows 0 and 1 are all that the link storage (and the reunitarisation) use
+  L Un = G::template expi_mul<true>(e, (T)(c.a[i] * c.dt), Ui);
   if (reunit) {
     // projection back onto SU(N) in double arithmetic
     using Gd = typename GroupOf<G::NC, double>::type;
@@ -68,125 +71,35 @@ __device__ __forceinline__ void update_link(const T* __restrict__ U, T* __restri
   }
 }
 
-// Update of link (x, i) from its staple sum S (the z-link thread also hops the charges).
-template <typename G, typename T, bool HOP>
-__device__ __forceinline__ void finish_link(T* __restrict__ Unew, T* __restrict__ E, T* __restrict__ rhoA,
-                                            T* __restrict__ rhoB, const Geom& g, const StepConst& c, Site x,
-                                            uint32_t s, int i, const typename G::Link& Ui,
-                                            const typename G::Link& S) {
-  using L = typename G::Link;
-  using A = typename G::Alg;
-  constexpr int NG = G::NG;
-  const int64_t Vp = g.Vp;
-  A f = G::proj_mul(Ui, S);
-  A e;
-  load_alg(e, E, i, s, Vp);
-  const T kf = (T)(-c.dt / c.a[i]);
-#pragma unroll
-  for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
-  if (HOP && i == 2) {
-    const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
-    const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
-    A rb, ra;
-    load_alg(rb, rhoB, 0, sB, Vp);
-    load_alg(ra, rhoA, 0, sA, Vp);
-    A rbn = G::transport(Ui, rb);
-    A ran = G::transport_inv(Ui, ra);
-    store_alg(rbn, rhoB, 0, sB, Vp);
-    store_alg(ran, rhoA, 0, sA, Vp);
-    const T al = (T)c.a[2];
-#pragma unroll
-    for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
-  }
-  store_alg(e, E, i, s, Vp);
-  L Un = G::mul(G::expi(e, (T)(c.a[i] * c.dt)), Ui);
-  store_link(Un, Unew, i, s, Vp);
-}
-
 #ifndef GL_LF_WAVES
 #define GL_LF_WAVES 1
 #endif
-#ifndef GL_LF_PER_DIR
-#define GL_LF_PER_DIR 0
-#endif
-#ifndef GL_LF_PAIRS
-#define GL_LF_PAIRS 0
-#endif
-
 // One thread per site, the three directions in turn.
+constexpr int LF_BS = 256;
 template <typename G, typename T, bool HOP>
-__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
-                                                               T* __restrict__ E, T* __restrict__ rhoA,
-                                                               T* __restrict__ rhoB, Geom g, StepConst c,
-                                                               ColMap m) {
+__global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
+                                                                 T* __restrict__ E, T* __restrict__ rhoA,
+                                                                 T* __restrict__ rhoB, Geom g, StepConst c,
+                                                                 ColMap m) {
   Site x;
   uint32_t s;
-  if (!col_map_site(g, m, blockIdx.x, threadIdx.x, blockDim.x, x, s)) return;
+  if (!col_map_site(g, m, blockIdx.x, threadIdx.x, LF_BS, x, s)) return;
+  const GlobalLinks<T> f{U, g.Vp};
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
 #pragma unroll 1
-  for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
-}
-
-// One thread per site, staple sums of all three directions by unordered planes.
-template <typename G, typename T, bool HOP>
-__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog_pairs(const T* __restrict__ U, T* __restrict__ Unew,
-                                                                     T* __restrict__ E, T* __restrict__ rhoA,
-                                                                     T* __restrict__ rhoB, Geom g, StepConst c,
-                                                                     ColMap m) {
-  using L = typename G::Link;
-  Site x;
-  uint32_t s;
-  if (!col_map_site(g, m, blockIdx.x, threadIdx.x, blockDim.x, x, s)) return;
-  const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
-  L Ux[3], S[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) load_link(Ux[i], U, i, s, g.Vp);
-  staple_sums_pairs<G, T>(U, g, x, Ux, inv_a2, S);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) finish_link<G, T, HOP>(Unew, E, rhoA, rhoB, g, c, x, s, i, Ux[i], S[i]);
-}
-
-// One thread per link: direction i = blockIdx.y, uniform over the block.
-template <typename G, typename T, bool HOP>
-__global__ void __launch_bounds__(256, GL_LF_WAVES) k_leapfrog_dir(const T* __restrict__ U, T* __restrict__ Unew,
-                                                                   T* __restrict__ E, T* __restrict__ rhoA,
-                                                                   T* __restrict__ rhoB, Geom g, StepConst c) {
-  const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (s >= (uint32_t)g.V) return;
-  Site x;
-  x.x = (int)(s % (uint32_t)g.nt);
-  x.y = (int)((s / (uint32_t)g.nt) % (uint32_t)g.nt);
-  x.z = (int)(s / (uint32_t)g.layer);
-  const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
-  const int i = blockIdx.y;
-  update_link<G, T, HOP>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
+  for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(f, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
 }
 
 template <typename G, typename T>
 void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
                      hipStream_t st) {
-  const int bs = 256;
-  const int64_t nb = (g.V + bs - 1) / bs;
-  if (GL_LF_PER_DIR) {
-    if (c.hop)
-      hipLaunchKernelGGL((k_leapfrog_dir<G, T, true>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
-    else
-      hipLaunchKernelGGL((k_leapfrog_dir<G, T, false>), dim3((unsigned)nb, 3), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c);
-  } else if (GL_LF_PAIRS) {
-    const ColMap m = col_map(g, bs);
-    const unsigned nbc = col_map_blocks(g, m);
-    if (c.hop)
-      hipLaunchKernelGGL((k_leapfrog_pairs<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-    else
-      hipLaunchKernelGGL((k_leapfrog_pairs<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-  } else {
-    const ColMap m = col_map(g, bs);
-    const unsigned nbc = col_map_blocks(g, m);
-    if (c.hop)
-      hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-    else
-      hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-  }
+  const int bs = LF_BS;
+  const ColMap m = col_map(g, bs);
+  const unsigned nbc = col_map_blocks(g, m);
+  if (c.hop)
+    hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+  else
+    hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
 }
 
 // ---- batched form: many events of different sizes in one launch --------------
@@ -224,12 +137,13 @@ __global__ void __launch_bounds__(256) k_batch_step(const EventDesc* __restrict_
     x.x = (int)(s % (uint32_t)d.g.nt);
     x.y = (int)((s / (uint32_t)d.g.nt) % (uint32_t)d.g.nt);
     x.z = (int)(s / (uint32_t)d.g.layer);
+    const GlobalLinks<T> f{U, d.g.Vp};
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       if (hop)
-        update_link<G, T, true>(U, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
+        update_link<G, T, true>(f, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
       else
-        update_link<G, T, false>(U, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
+        update_link<G, T, false>(f, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
     }
   }
 }
