@@ -701,13 +701,14 @@ static int batch_prepare(glasma_batch* b, int bs, BatchConst* bc) {
     d.g = c->g;
     // the buffer current now is current at steps of this parity
     const bool even_now = (s0 & 1) == 0;
+    auto rel = [&](void* ptr) { return (uint64_t)((char*)ptr - b->pool); };
     void* cur = c->cur ? c->b.U_alt : c->b.U;
     void* oth = c->cur ? c->b.U : c->b.U_alt;
-    d.Ueven = even_now ? cur : oth;
-    d.Uodd = even_now ? oth : cur;
-    d.E = c->b.E;
-    d.rhoA = c->b.rhoA;
-    d.rhoB = c->b.rhoB;
+    d.Ueven = rel(even_now ? cur : oth);
+    d.Uodd = rel(even_now ? oth : cur);
+    d.E = rel(c->b.E);
+    d.rhoA = rel(c->b.rhoA);
+    d.rhoB = rel(c->b.rhoB);
     d.item0 = (uint32_t)items.size();
     d.off0 = c->offA;
     d.hops0 = hop_count(c, s0 - 1);
@@ -733,7 +734,7 @@ static void batch_launch_one(glasma_batch* b, const BatchConst& bc, int bs, int 
   const int g = grid > 0 ? grid : (int)bc.items;
   glasma_ctx* c0 = b->ev[0];
   dispatch(c0, [&]<typename G, typename T>() -> int {
-    launch_batch_step<G, T>(b->d_ev, b->d_item_event, bc, b->d_ctr, g, bs, b->stream);
+    launch_batch_step<G, T>(b->pool, b->d_ev, b->d_item_event, bc, b->d_ctr, g, bs, b->stream);
     return 0;
   });
   launch_batch_tick(b->d_ctr, b->stream);

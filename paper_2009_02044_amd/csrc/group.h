@@ -64,6 +64,10 @@ template <typename T> struct Su2 {
   // (U - U^dag)/(2i) = q.s  ->  components 2 q_a
   static GL_HD Alg proj(const Link& m) { Alg r; r.c[0] = 2 * m.q[1]; r.c[1] = 2 * m.q[2]; r.c[2] = 2 * m.q[3]; return r; }
   static GL_HD T retr(const Link& m) { return 2 * m.q[0]; }               // Re Tr
+  // Re Tr(a b^dag)
+  static GL_HD T retr_mul_dag(const Link& a, const Link& b) {
+    return 2 * (a.q[0] * b.q[0] + a.q[1] * b.q[1] + a.q[2] * b.q[2] + a.q[3] * b.q[3]);
+  }
   // proj(a b): only the vector part of the product
   static GL_HD Alg proj_mul(const Link& a, const Link& b) {
     Alg r;
@@ -259,6 +263,18 @@ template <typename T> struct Su3 {
     return r;
   }
   static GL_HD T retr(const Link& m) { return m.re[0][0] + m.re[1][1] + m.re[2][2]; }
+  // Re Tr(a b^dag) = sum_ik Re(a_ik conj(b_ik))
+  static GL_HD T retr_mul_dag(const Link& a, const Link& b) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s = fmx(a.re[i][k], b.re[i][k], s);
+        s = fmx(a.im[i][k], b.im[i][k], s);
+      }
+    return s;
+  }
   // proj(M) of a product M = a b or a b^dag without forming M: each off-diagonal
   // component is one fused chain over the two entries it combines, and only the
   // imaginary diagonal of M is formed (its real part drops out).
@@ -487,15 +503,70 @@ template <typename T> struct Su3 {
     return r;
   }
   // U^dag X U
-  static GL_HD Alg transport(const Link& u, const Alg& x) {
-    Link X = herm(x, T(1));
-    return alg_of_herm(mul(dag_mul(u, X), u));
+  // Components of M = W X V for hermitian X = x^a t^a, with (W, V) = (u^dag, u) (INV
+  // false) or (u, u^dag) (INV true).  M is hermitian, so only its upper triangle and the
+  // real part of its diagonal are formed: Y = X V uses the real diagonal of X, then
+  // M_pq = sum_k W_pk Y_kq for p <= q.
+  template <bool INV>
+  static GL_HD Alg sandwich(const Link& u, const Alg& x) {
+    const Herm q = herm_c(x, T(1));
+    // X entries: X_pp = d_p, X_pq = r + i im above the diagonal, conjugate below
+    const int UP[3][3] = {{-1, 0, 1}, {0, -1, 2}, {1, 2, -1}};
+    auto vr = [&](int k, int j) { return INV ? u.re[j][k] : u.re[k][j]; };
+    auto vi = [&](int k, int j) { return INV ? -u.im[j][k] : u.im[k][j]; };
+    auto wr = [&](int p, int k) { return INV ? u.re[p][k] : u.re[k][p]; };
+    auto wi = [&](int p, int k) { return INV ? u.im[p][k] : -u.im[k][p]; };
+    T yr[3][3], yi[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = q.d[i] * vr(i, j), si = q.d[i] * vi(i, j);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (k == i) continue;
+          const int n = UP[i][k];
+          const T xr = q.r[n], xi = i < k ? q.i[n] : -q.i[n];
+          sr = fmx(xr, vr(k, j), sr);
+          sr = fmx(-xi, vi(k, j), sr);
+          si = fmx(xr, vi(k, j), si);
+          si = fmx(xi, vr(k, j), si);
+        }
+        yr[i][j] = sr; yi[i][j] = si;
+      }
+    T mr[3][3], mi[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int j = p; j < 3; ++j) {
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          sr = fmx(wr(p, k), yr[k][j], sr);
+          sr = fmx(-wi(p, k), yi[k][j], sr);
+          if (j != p) {
+            si = fmx(wr(p, k), yi[k][j], si);
+            si = fmx(wi(p, k), yr[k][j], si);
+          }
+        }
+        mr[p][j] = sr; mi[p][j] = si;
+      }
+    const T is3 = T(0.57735026918962576451);
+    Alg r;
+    r.c[0] = T(2) * mr[0][1];
+    r.c[1] = T(-2) * mi[0][1];
+    r.c[2] = mr[0][0] - mr[1][1];
+    r.c[3] = T(2) * mr[0][2];
+    r.c[4] = T(-2) * mi[0][2];
+    r.c[5] = T(2) * mr[1][2];
+    r.c[6] = T(-2) * mi[1][2];
+    r.c[7] = (mr[0][0] + mr[1][1] - T(2) * mr[2][2]) * is3;
+    return r;
   }
+  // U^dag X U
+  static GL_HD Alg transport(const Link& u, const Alg& x) { return sandwich<false>(u, x); }
   // U X U^dag
-  static GL_HD Alg transport_inv(const Link& u, const Alg& x) {
-    Link X = herm(x, T(1));
-    return alg_of_herm(mul_dag(mul(u, X), u));
-  }
+  static GL_HD Alg transport_inv(const Link& u, const Alg& x) { return sandwich<true>(u, x); }
   // principal -i Log W for W close to 1 (all eigen-angles well inside (-pi/2, pi/2)):
   // fixed point of H <- H + proj(exp(-iH/2) W exp(-iH/2)), which converges with the
   // cube of the symmetric-splitting error; at the fixed point W = exp(iH).

@@ -11,13 +11,15 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
                      hipStream_t st);
 
 // Batched form (step.hip): one descriptor per event, workgroups loop over work items.
+// Buffers are byte offsets into the batch's pool, whose base is a kernel argument (so
+// the compiler knows every access is to device memory).
 struct EventDesc {
   Geom g;
-  const void* Ueven;  // link buffer that is current at even steps
-  const void* Uodd;   // link buffer that is current at odd steps
-  void* E;
-  void* rhoA;
-  void* rhoB;
+  uint64_t Ueven;     // link buffer that is current at even steps
+  uint64_t Uodd;      // link buffer that is current at odd steps
+  uint64_t E;
+  uint64_t rhoA;
+  uint64_t rhoB;
   uint32_t item0;     // first work item of the event
   int32_t off0;       // charge offset at the reference step
   int64_t hops0;      // hop count S(s_ref - 1) at the reference step
@@ -30,8 +32,8 @@ struct BatchConst {
   uint32_t items;
 };
 template <typename G, typename T>
-void launch_batch_step(const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc, const int64_t* ctr,
-                       int grid, int bs, hipStream_t st);
+void launch_batch_step(char* pool, const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc,
+                       const int64_t* ctr, int grid, int bs, hipStream_t st);
 void launch_batch_tick(int64_t* ctr, hipStream_t st);
 
 // Observables at the current integer time, written to `out` (device, double):

@@ -106,19 +106,32 @@ GL_HD void load_comps(T (&v)[W], const S* __restrict__ dir, uint32_t s) {
     for (int k = 0; k < Sh::TL; ++k) v[Sh::NF * Sh::VW + k] = (T)t[k];
   }
 }
+// Stores of kernel outputs are marked non-temporal (streamed past the caches) unless
+// GL_NT_STORE is 0: no kernel reads back what it writes, and the stream would
+// otherwise displace the neighbour links that other work-groups still read.
+#ifndef GL_NT_STORE
+#define GL_NT_STORE 1
+#endif
+template <typename S> struct NVec16;
+template <> struct NVec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NVec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <typename T, typename S, int W>
 GL_HD void store_comps(const T (&v)[W], S* __restrict__ dir, uint32_t s) {
   using Sh = RecShape<S, W>;
-  using V16 = typename Vec16<S>::type;
+  using NV = typename NVec16<S>::type;
   char* rec = (char*)dir + (uint64_t)(s / RB) * Sh::BYTES;
   const uint32_t l = s % RB;
 #pragma unroll
   for (int q = 0; q < Sh::NF; ++q) {
-    V16 x;
-    S* e = (S*)&x;
+    NV x;
 #pragma unroll
-    for (int k = 0; k < Sh::VW; ++k) e[k] = (S)v[q * Sh::VW + k];
-    *(V16*)(rec + q * (RB * 16) + l * 16) = x;
+    for (int k = 0; k < Sh::VW; ++k) x[k] = (S)v[q * Sh::VW + k];
+    NV* dst = (NV*)(rec + q * (RB * 16) + l * 16);
+#if GL_NT_STORE && defined(__HIP_DEVICE_COMPILE__)
+    __builtin_nontemporal_store(x, dst);
+#else
+    *dst = x;
+#endif
   }
   if constexpr (Sh::TL > 0) {
     S* t = (S*)(rec + Sh::NF * (RB * 16) + l * (Sh::TL * sizeof(S)));
@@ -163,6 +176,21 @@ template <typename T, typename S>
 GL_HD void load_link(M3<T>& l, const S* __restrict__ U, int i, uint32_t s, int64_t Vp) {
   T v[SU3_STORED];
   load_comps<T, S, SU3_STORED>(v, field_dir(U, i, SU3_STORED, Vp), s);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      l.re[r][k] = v[2 * (3 * r + k)];
+      l.im[r][k] = v[2 * (3 * r + k) + 1];
+    }
+  complete_row2(l);
+}
+// link from its stored reals (SU(3): rows 0 and 1, row 2 rebuilt)
+template <typename T> GL_HD void link_from_stored(Q2<T>& l, const T (&v)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) l.q[k] = v[k];
+}
+template <typename T> GL_HD void link_from_stored(M3<T>& l, const T (&v)[SU3_STORED]) {
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll

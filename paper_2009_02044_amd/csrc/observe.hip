@@ -19,11 +19,12 @@ namespace gl {
 
 constexpr int NQ = 9;   // eps, pL, pT, SL, |G|^2, |rho|^2, max|G^a|, max unitarity, nonfinite
 constexpr int OBS_BS = 256;
+#ifndef GL_OBS_OWN
+#define GL_OBS_OWN OWN_LDS
+#endif
 
-static int obs_blocks_per_layer(const Geom& g) {
-  int64_t nb = (g.layer + OBS_BS - 1) / OBS_BS;
-  return (int)(nb < 16 ? nb : 16);
-}
+// one site per thread: the blocks of a layer cover it exactly once
+static int obs_blocks_per_layer(const Geom& g) { return (int)((g.layer + OBS_BS - 1) / OBS_BS); }
 size_t observe_partial_doubles(const Geom& g) {
   return (size_t)obs_blocks_per_layer(g) * g.nz * NQ;
 }
@@ -45,7 +46,7 @@ template <typename A> __device__ __forceinline__ double norm2(const A& a) {
   return s;
 }
 
-template <typename G, typename T>
+template <typename G, typename T, bool XS>
 __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, const T* __restrict__ E,
                                                     const T* __restrict__ rhoA, const T* __restrict__ rhoB,
                                                     Geom g, StepConst c, double* __restrict__ partial) {
@@ -56,30 +57,43 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
   const int z = blockIdx.y;
   const int nbx = gridDim.x;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
+  __shared__ typename Vec16<T>::type slot[3 * OwnSlot<G, T>::NCH * OBS_BS];
+  const GlobalLinks<T> fetch{U, Vp};
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * OBS_BS + threadIdx.x; t < g.layer; t += (int64_t)nbx * OBS_BS) {
-    const int64_t s = (int64_t)z * g.layer + t;
+  // blocks start at multiples of 64 sites of the layer, so rows stay whole for XS
+  const int64_t t = (int64_t)blockIdx.x * OBS_BS + threadIdx.x;
+  if (t < g.layer) {
+    const uint32_t s = (uint32_t)((int64_t)z * g.layer + t);
     Site x;
     x.x = (int)(t % g.nt);
     x.y = (int)(t / g.nt);
     x.z = z;
+    // force terms of the E update, and the forward plaquettes, in double precision
+    const OwnLinks<G, T, GL_OBS_OWN> own(fetch, s, slot, threadIdx.x, OBS_BS);
+    A f[3];
+    PlaqObs<G> pl;
+    plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &pl);
     double e2[3];
     A ebar[2];
     bool bad = false;
+    // one direction at a time (i is a run-time value: members are selected, not indexed)
+#pragma unroll 1
     for (int i = 0; i < 3; ++i) {
-      L S = staple_sum<G, T>(U, g, x, i, inv_a2);
-      L Ui;
-      load_link(Ui, U, i, s, Vp);
-      A f = G::proj_mul(Ui, S);
+      const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
       A eo, en;
       load_alg(eo, E, i, s, Vp);
-      for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k] - c.dt / c.a[i] * f.c[k];
+      for (int k = 0; k < NG; ++k) {
+        const double fk = i == 0 ? f[0].c[k] : (i == 1 ? f[1].c[k] : f[2].c[k]);
+        en.c[k] = eo.c[k] - c.dt / ai * fk;
+      }
       // semi-implicit scheme: E(t + dt/2) needs the next implicit solve; its
       // observables use E(t - dt/2) for both half steps
       if (c.scheme == 1)
         for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k];
+      L Ui;
+      own(Ui, i);
       if (c.hop && i == 2 && c.scheme == 0) {
         A rb, ra;
         load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
@@ -88,24 +102,28 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
         for (int k = 0; k < NG; ++k) en.c[k] += c.a[2] * (ran.c[k] - rb.c[k]);
       }
       for (int k = 0; k < NG; ++k) bad |= !isfinite(en.c[k]);
-      e2[i] = 0.5 * (norm2(eo) + norm2(en));
-      if (i < 2)
-        for (int k = 0; k < NG; ++k) ebar[i].c[k] = 0.5 * (eo.c[k] + en.c[k]);
+      const double ei = 0.5 * (norm2(eo) + norm2(en));
+      e2[0] = i == 0 ? ei : e2[0];
+      e2[1] = i == 1 ? ei : e2[1];
+      e2[2] = i == 2 ? ei : e2[2];
+      for (int k = 0; k < NG; ++k) {
+        const double b = 0.5 * (eo.c[k] + en.c[k]);
+        ebar[0].c[k] = i == 0 ? b : ebar[0].c[k];
+        ebar[1].c[k] = i == 1 ? b : ebar[1].c[k];
+      }
       double uv = G::unit_violation(Ui);
       bad |= !isfinite(uv);
       acc[7] = fmax(acc[7], uv);
     }
+    // B^2 from the forward plaquettes U_{x,y}, U_{y,z} and U_{z,x} = U_{x,z}^dag (same
+    // real trace); F_yz = P(U_{y,z}), F_zx = P(U_{z,x}) = -P(U_{x,z})
     const double nc = (double)G::NC;
-    L Pxy = plaquette<G, T>(U, g, x, 0, 1);
-    L Pyz = plaquette<G, T>(U, g, x, 1, 2);
-    L Pzx = plaquette<G, T>(U, g, x, 2, 0);
-    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - G::retr(Pxy));
-    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - G::retr(Pyz));
-    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - G::retr(Pzx));
-    A Fyz = G::proj(Pyz), Fzx = G::proj(Pzx);
+    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - pl.tr[0]);
+    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - pl.tr[2]);
+    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - pl.tr[1]);
     const double kyz = 1.0 / (c.a[1] * c.a[2]), kzx = 1.0 / (c.a[2] * c.a[0]);
     double sl = 0.0;
-    for (int k = 0; k < NG; ++k) sl -= ebar[0].c[k] * Fzx.c[k] * kzx - ebar[1].c[k] * Fyz.c[k] * kyz;
+    for (int k = 0; k < NG; ++k) sl -= -ebar[0].c[k] * pl.p[1].c[k] * kzx - ebar[1].c[k] * pl.p[2].c[k] * kyz;
     const double EL2 = e2[2], ET2 = e2[0] + e2[1], BL2 = bxy, BT2 = byz + bzx;
     acc[0] += 0.5 * (EL2 + ET2 + BL2 + BT2);
     acc[1] += 0.5 * (ET2 + BT2 - EL2 - BL2);
@@ -116,7 +134,9 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     load_alg(r, rhoA, 0, site_index(g, x.x, x.y, slotA(z, c.offA, g.nz)), Vp);
     load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
     for (int k = 0; k < NG; ++k) { r.c[k] += rb.c[k]; G_.c[k] = -r.c[k]; }
+#pragma unroll 1
     for (int i = 0; i < 3; ++i) {
+      const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
       Site xm = shifted(g, x, i, -1);
       const int64_t sm = idx(g, xm);
       L Um;
@@ -125,7 +145,7 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
       load_alg(eh, E, i, s, Vp);
       load_alg(em, E, i, sm, Vp);
       A tr = G::transport(Um, em);
-      for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tr.c[k]) / c.a[i];
+      for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tr.c[k]) / ai;
     }
     acc[4] += norm2(G_);
     acc[5] += norm2(r);
@@ -197,7 +217,11 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
                     const StepConst& c, double* partial, double* out, hipStream_t st) {
   using Gd = typename GroupOf<G::NC, double>::type;
   const int nbx = obs_blocks_per_layer(g);
-  hipLaunchKernelGGL((k_observe<Gd, T>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+  // blocks start at multiples of 64 sites of a layer: rows lie in wavefronts when nt divides 64
+  if (rows_in_wavefronts(g.nt))
+    hipLaunchKernelGGL((k_observe<Gd, T, true>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+  else
+    hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 

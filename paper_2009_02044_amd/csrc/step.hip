@@ -1,14 +1,13 @@
 // Leapfrog step with the CPIC charge hop (Sec. 3: eqs. lattice_1, lattice_2,
 // plaquette, continuity and the nearest-grid-point transport rule).
 //
-// One thread owns one site x and its three links.  For each direction i it forms
-// the staple sum
-//   S_i = sum_{j != i} a_j^-2 [ U_j(x+i) U_i^dag(x+j) U_j^dag(x)
-//                               + U_j^dag(x+i-j) U_i^dag(x-j) U_j(x-j) ],
-// so that U_i(x) S_i = sum_j a_j^-2 (U_{i,j} + U_{i,-j}), and updates
-//   E_i += dt ( -(1/a_i) proj(U_i S_i) + j_i ),   U_i' = exp(i a_i dt E_i) U_i,
+// One thread owns one site x and its three links.  It forms the force terms
+//   f_i = sum_{j != i} a_j^-2 P(U_{i,j}(x) + U_{i,-j}(x))
+// plaquette by plaquette (stencil.h: plaquette_forces; a forward plaquette serves
+// both of its directions), then for each direction updates
+//   E_i += dt ( -(1/a_i) f_i + j_i ),   U_i' = exp(i a_i dt E_i) U_i,
 // writing U' into the second link buffer (old links stay readable by the
-// neighbours) and E in place.  On a hop step the z-link thread also moves both
+// neighbours) and E in place.  On a hop step the z-link update also moves both
 // charge populations one cell with parallel transport and adds the current that
 // satisfies the continuity equation exactly:
 //   B (+z): rho_B(x+z) <- U_z^dag(x) rho_B(x) U_z(x),     j_z(x) -= (a_L/dt) rho_B(x)
@@ -19,28 +18,40 @@
 
 namespace gl {
 
-// Update of link (x, i): staples, E, CPIC hop (z links on hop steps), exp, new link.
-// fetch(l, d, s) supplies the links at time t (from the work-group's LDS tile or memory).
-template <typename G, typename T, bool HOP, typename F>
-__device__ __forceinline__ void update_link(const F& fetch, T* __restrict__ Unew, T* __restrict__ E,
-                                            T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
-                                            const StepConst& c, const double* inv_a2, Site x, uint32_t s, int i,
-                                            bool reunit = false) {
+template <typename R> __device__ __forceinline__ M3<double> to_double(const M3<R>& a) {
+  M3<double> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { r.re[i][j] = (double)a.re[i][j]; r.im[i][j] = (double)a.im[i][j]; }
+  return r;
+}
+template <typename R> __device__ __forceinline__ Q2<double> to_double(const Q2<R>& a) {
+  Q2<double> r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.q[k] = (double)a.q[k];
+  return r;
+}
+
+// Update of link (x, i) from the force term f_i of plaquette_forces (F_i = -f_i / a_i);
+// the z-link thread also hops the charges.
+template <typename G, typename T, bool HOP>
+__device__ __forceinline__ void finish_link(const typename G::Link& Ui, const typename G::Alg& fi,
+                                            T* __restrict__ Unew, T* __restrict__ E, T* __restrict__ rhoA,
+                                            T* __restrict__ rhoB, const Geom& g, const StepConst& c, Site x,
+                                            uint32_t s, int i, bool reunit) {
   using L = typename G::Link;
   using A = typename G::Alg;
   constexpr int NG = G::NG;
   const int64_t Vp = g.Vp;
-  const double w1 = inv_a2[other_lo(i)], w2 = inv_a2[other_hi(i)];
-  L S = staple_sum_scaled_f<G>(fetch, g, x, i, (T)(w1 / w2));
-  L Ui;
-  fetch(Ui, i, s);
-  A f = G::proj_mul(Ui, S);
+  // i is a run-time value: select the spacing (no indexed local array)
+  const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
   A e;
   load_alg(e, E, i, s, Vp);
-  const T kf = (T)(-c.dt / c.a[i] * w2);
+  const T kf = (T)(-c.dt / ai);
 #pragma unroll
-  for (int k = 0; k < NG; ++k) e.c[k] += kf * f.c[k];
-  if (HOP && i == 2) {
+  for (int k = 0; k < NG; ++k) e.c[k] = fmx(kf, fi.c[k], e.c[k]);
+  if (HOP && c.hop && i == 2) {
     const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
     const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
     A rb, ra;
@@ -56,38 +67,68 @@ __device__ __forceinline__ void update_link(const F& fetch, T* __restrict__ Unew
     for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
   }
   store_alg(e, E, i, s, Vp);
-  // rows 0 and 1 are all that the link storage (and the reunitarisation) use
-  L Un = G::template expi_mul<true>(e, (T)(c.a[i] * c.dt), Ui);
+  L Un = G::template expi_mul<true>(e, (T)(ai * c.dt), Ui);
   if (reunit) {
     // projection back onto SU(N) in double arithmetic
     using Gd = typename GroupOf<G::NC, double>::type;
-    typename Gd::Link ud;
-    const T* un = reinterpret_cast<const T*>(&Un);
-    double* dd = reinterpret_cast<double*>(&ud);
-    for (int k = 0; k < (int)(sizeof(L) / sizeof(T)); ++k) dd[k] = (double)un[k];
-    store_link(Gd::reunit(ud), Unew, i, s, Vp);
+    store_link(Gd::reunit(to_double(Un)), Unew, i, s, Vp);
   } else {
     store_link(Un, Unew, i, s, Vp);
   }
 }
+
+// The whole site update from plaquette forces.
+template <typename G, typename T, bool HOP, bool XS, int OWN>
+__device__ __forceinline__ void update_site(const T* __restrict__ U, T* __restrict__ Unew, T* __restrict__ E,
+                                            T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
+                                            const StepConst& c, const double* inv_a2, Site x, uint32_t s,
+                                            bool reunit, typename Vec16<T>::type* slot, uint32_t TB) {
+  using L = typename G::Link;
+  const GlobalLinks<T> fetch{U, g.Vp};
+  const OwnLinks<G, T, OWN> own(fetch, s, slot, threadIdx.x, TB);
+  typename G::Alg f[3];
+  plaquette_forces<G, XS>(fetch, own, g, x, inv_a2, f);
+#pragma unroll 1
+  for (int i = 0; i < 3; ++i) {
+    L Ui;
+    own(Ui, i);
+    typename G::Alg fi;
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) fi.c[k] = i == 0 ? f[0].c[k] : (i == 1 ? f[1].c[k] : f[2].c[k]);
+    finish_link<G, T, HOP>(Ui, fi, Unew, E, rhoA, rhoB, g, c, x, s, i, reunit);
+  }
+}
+
+#ifndef GL_OWN64
+#define GL_OWN64 OWN_LDS
+#endif
+#ifndef GL_OWN32
+#define GL_OWN32 OWN_LDS
+#endif
+template <typename G, typename T> struct OwnMode {
+  static constexpr int value = sizeof(T) == 8 ? GL_OWN64 : GL_OWN32;
+};
+// LDS for the own-link slots of a work-group of TB threads (one element when unused)
+template <typename G, typename T, int TB> struct OwnLds {
+  static constexpr int N = OwnMode<G, T>::value == OWN_LDS ? 3 * OwnSlot<G, T>::NCH * TB : 1;
+};
 
 #ifndef GL_LF_WAVES
 #define GL_LF_WAVES 1
 #endif
 // One thread per site, the three directions in turn.
 constexpr int LF_BS = 256;
-template <typename G, typename T, bool HOP>
+template <typename G, typename T, bool HOP, bool XS>
 __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
                                                                  T* __restrict__ E, T* __restrict__ rhoA,
                                                                  T* __restrict__ rhoB, Geom g, StepConst c,
                                                                  ColMap m) {
   Site x;
   uint32_t s;
+  __shared__ typename Vec16<T>::type slot[OwnLds<G, T, LF_BS>::N];
   if (!col_map_site(g, m, blockIdx.x, threadIdx.x, LF_BS, x, s)) return;
-  const GlobalLinks<T> f{U, g.Vp};
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
-#pragma unroll 1
-  for (int i = 0; i < 3; ++i) update_link<G, T, HOP>(f, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, i);
+  update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
 }
 
 template <typename G, typename T>
@@ -96,13 +137,19 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
   const int bs = LF_BS;
   const ColMap m = col_map(g, bs);
   const unsigned nbc = col_map_blocks(g, m);
-  if (c.hop)
-    hipLaunchKernelGGL((k_leapfrog<G, T, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-  else
-    hipLaunchKernelGGL((k_leapfrog<G, T, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+  // rows inside wavefronts: x neighbours from other lanes
+  const bool xs = rows_in_wavefronts(g.nt);
+  if (c.hop) {
+    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+    else hipLaunchKernelGGL((k_leapfrog<G, T, true, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+  } else {
+    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, false, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+    else hipLaunchKernelGGL((k_leapfrog<G, T, false, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+  }
 }
 
 // ---- batched form: many events of different sizes in one launch --------------
+
 // Work item = `bs` consecutive sites of one event; workgroups loop over the items
 // (persistent when the grid is smaller than the item count).  The step number comes
 // from device memory so that a captured graph of several steps replays correctly:
@@ -110,7 +157,7 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
 GL_HD int64_t hop_count_dev(int64_t s, int64_t p, int64_t q) { return ((2 * s + 1) * p + q) / (2 * q); }
 
 template <typename G, typename T>
-__global__ void __launch_bounds__(256) k_batch_step(const EventDesc* __restrict__ ev,
+__global__ void __launch_bounds__(256) k_batch_step(char* __restrict__ pool, const EventDesc* __restrict__ ev,
                                                     const uint32_t* __restrict__ item_event, BatchConst bc,
                                                     const int64_t* __restrict__ ctr) {
   const int64_t st = ctr[0];
@@ -118,6 +165,7 @@ __global__ void __launch_bounds__(256) k_batch_step(const EventDesc* __restrict_
   const bool hop = S1 > S0;
   const bool reunit = bc.reunit_every > 0 && ((st + 1) % bc.reunit_every) == 0;
   const double inv_a2[3] = {1.0 / (bc.a[0] * bc.a[0]), 1.0 / (bc.a[1] * bc.a[1]), 1.0 / (bc.a[2] * bc.a[2])};
+  __shared__ typename Vec16<T>::type slot[OwnLds<G, T, 256>::N];
   for (uint32_t item = blockIdx.x; item < bc.items; item += gridDim.x) {
     const EventDesc d = ev[item_event[item]];
     const uint32_t s = (item - d.item0) * blockDim.x + threadIdx.x;
@@ -131,20 +179,22 @@ __global__ void __launch_bounds__(256) k_batch_step(const EventDesc* __restrict_
     c.offB = (int)off;
     c.scheme = 0;
     const bool odd = (st & 1) != 0;
-    const T* U = (const T*)(odd ? d.Uodd : d.Ueven);
-    T* Un = (T*)(odd ? d.Ueven : d.Uodd);
+    const T* U = (const T*)(pool + (odd ? d.Uodd : d.Ueven));
+    T* Un = (T*)(pool + (odd ? d.Ueven : d.Uodd));
     Site x;
     x.x = (int)(s % (uint32_t)d.g.nt);
     x.y = (int)((s / (uint32_t)d.g.nt) % (uint32_t)d.g.nt);
     x.z = (int)(s / (uint32_t)d.g.layer);
-    const GlobalLinks<T> f{U, d.g.Vp};
-#pragma unroll 1
-    for (int i = 0; i < 3; ++i) {
-      if (hop)
-        update_link<G, T, true>(f, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
-      else
-        update_link<G, T, false>(f, Un, (T*)d.E, (T*)d.rhoA, (T*)d.rhoB, d.g, c, inv_a2, x, s, i, reunit);
-    }
+    // item = 64-aligned sites of one event: rows lie in wavefronts when nt divides 64
+    constexpr int K = OwnMode<G, T>::value;
+    T *E = (T*)(pool + d.E), *rA = (T*)(pool + d.rhoA), *rB = (T*)(pool + d.rhoB);
+    const uint32_t TB = blockDim.x;
+    const Geom g = d.g;
+    // the hop branch inside is uniform over the launch (HOP = true only enables it)
+    if (rows_in_wavefronts(g.nt))
+      update_site<G, T, true, true, K>(U, Un, E, rA, rB, g, c, inv_a2, x, s, reunit, slot, TB);
+    else
+      update_site<G, T, true, false, K>(U, Un, E, rA, rB, g, c, inv_a2, x, s, reunit, slot, TB);
   }
 }
 
@@ -157,16 +207,17 @@ __global__ void k_batch_tick(int64_t* ctr) {
 }
 
 template <typename G, typename T>
-void launch_batch_step(const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc, const int64_t* ctr,
-                       int grid, int bs, hipStream_t st) {
-  hipLaunchKernelGGL((k_batch_step<G, T>), dim3((unsigned)grid), dim3((unsigned)bs), 0, st, ev, item_event, bc, ctr);
+void launch_batch_step(char* pool, const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc,
+                       const int64_t* ctr, int grid, int bs, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch_step<G, T>), dim3((unsigned)grid), dim3((unsigned)bs), 0, st, pool, ev, item_event, bc,
+                     ctr);
 }
 void launch_batch_tick(int64_t* ctr, hipStream_t st) { hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, st, ctr); }
 
-template void launch_batch_step<Su2<double>, double>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
-template void launch_batch_step<Su3<double>, double>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
-template void launch_batch_step<Su2<float>, float>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
-template void launch_batch_step<Su3<float>, float>(const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su2<double>, double>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su3<double>, double>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su2<float>, float>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
+template void launch_batch_step<Su3<float>, float>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
 
 template void launch_leapfrog<Su2<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);
 template void launch_leapfrog<Su3<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);
