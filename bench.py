@@ -348,7 +348,7 @@ def main():
                    "dt": w.dt, "scheme": "leapfrog", "obs_every": 16},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
-                     "kernel": "k_leapfrog<Su3<double>,double>", "kernel_ms": r64["kernel_ms"],
+                     "kernel": "k_leapfrog<Su3<double>,double,hop,xs=true>", "kernel_ms": r64["kernel_ms"],
                      "bytes_per_site_update": bpsu, "bytes_per_launch": launch_bytes},
         "checks": {"gauss_rel": r64["gauss_rel"], "unitarity": r64["unitarity"]},
         "forms": forms,

@@ -225,3 +225,29 @@ def test_full_size_plain_su3_sampled():
         s = (z * w.nt + y) * w.nt + x
         E_got = su.from_components(after["E"][:, :, s], 3)
         np.testing.assert_allclose(E_got, E_ref, atol=1e-12 * max(1.0, np.abs(E_ref).max()))
+
+
+@pytest.mark.parametrize("nc,nz,nt", [(3, 3, 64), (3, 4, 32), (2, 4, 16), (3, 4, 12)])
+def test_leapfrog_generic_state_row_layouts(nc, nz, nt):
+    """Per-component parity on a generic state (random links and fields, charges from the
+    Gauss law) for rows of 64, 32 and 16 sites (a wavefront holds whole rows: x neighbours
+    come from adjacent lanes, backward -x plaquettes from the neighbour lane) and of 12
+    sites (rows cross wavefronts: every neighbour from memory); steps 1..6 include hops."""
+    pkg = lattice_or_skip()
+    say(f"case: generic state su{nc} {nz}x{nt}x{nt}")
+    dims = (nz, nt, nt)
+    ng = nc * nc - 1
+    p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=0.5)
+    Ua = synth.normal(200 + nt, (3,) + dims + (ng,), 0.6)
+    Ea = synth.normal(300 + nt, (3,) + dims + (ng,), 0.3)
+    st = init_mv.state_from_algebra(Ua, Ea, p)
+    lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=0.5, fp=64)
+    lat.init_state(*to_comp(st), step0=0)
+    for s in range(6):
+        st = lattice.leapfrog_step(st)
+        lat.step(1)
+        errs = state_errs(lat.get_state(), st)
+        assert max(errs.values()) < 1e-10, (s, errs)
+    go, oo = lat.observables(), observables.observables(st)
+    _obs_close(go, oo, 1e-10)
+    assert go["gauss_rel"] < 1e-12
