@@ -14,8 +14,9 @@ of N_z in {128,256,384} x N_T in {32,48,64}, 512 steps, HIP-graph replay, autotu
 tiling, event-averaged T^{mu nu}(z)), the semi-implicit scheme on the headline
 lattice, the differentiation form (gradient of the central-slab energy after 256 steps of
 a 256 x 32 x 32 lattice, FP32 forward with checkpoints every 32 steps, FP64 reverse pass),
-optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and the
-FP64 CPU oracle timed on the host.
+the local rest frame at the collision point after the collision (eps_loc from diagonalising
+T^{mu nu}), optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
+the FP64 CPU oracle timed on the host.
 """
 import argparse
 import hashlib
@@ -111,6 +112,38 @@ def run_plain(w, fp, steps, warmup, obs_every=16, scheme=0, tol=1e-12):
     o = pkg.Lattice.unpack_obs(obs, w.nz)
     out.update({"gauss_rel": o["gauss_rel"], "energy": o["energy"], "unitarity": o["unitarity"]})
     return out
+
+
+def run_rest_frame(w, after=224, every=32):
+    """Local rest frame at the collision point of the headline lattice (Sec. 4): the nuclei
+    (centres zB, zA, moving at the speed of light) meet at z_c = (zA + zB)/2 at
+    t_c = (zA - zB)/2; from then on every `every` steps, eps_loc, the frame velocity, tau,
+    eps_loc * tau and the pressure ratios 2 p_T / eps_loc, p_L / eps_loc at z_c (free
+    streaming: eps_loc ~ 1/tau, 2 p_T = eps_loc, p_L ~ 0).  FP64, GPU observables."""
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=64)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+    z_c, t_c = 0.5 * (w.zA + w.zB), 0.5 * (w.zA - w.zB)
+    kz = int(round(z_c / w.a_L))
+    s_c = int(round(t_c / w.dt))
+    obs = lat.obs_buffer()
+    lat.step(s_c)
+    rows = []
+    for k in range(after // every):
+        lat.step(every)
+        lat.observe(obs)
+        rf = lat.rest_frame(obs)
+        torch.cuda.synchronize()
+        o = pkg.Lattice.unpack_obs(obs, w.nz)
+        el, v = (float(x) for x in rf[:, kz].cpu().numpy())
+        eps, pL, pT, _ = (float(x) for x in o["tmunu_z"][:, kz])
+        tau = (s_c + (k + 1) * every) * w.dt - t_c
+        rows.append({"step": s_c + (k + 1) * every, "tau": tau, "eps_loc": el, "v": v,
+                     "eps_loc_tau": el * tau, "2pT_over_eps_loc": 2 * pT / el, "pL_over_eps_loc": pL / el})
+    return {"workload": w.name, "z_c": z_c, "t_c": t_c, "rows": rows}
 
 
 def run_batched(steps, warmup, graph_chunk=16):
@@ -265,6 +298,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=512)
     ap.add_argument("--semi-steps", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-rest-frame", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
     ap.add_argument("--precision-steps", type=int, default=2048)
@@ -320,6 +354,12 @@ def main():
         ra = run_adjoint(wa, wa.steps, 32)
         forms["adjoint_fp32_fwd_fp64_rev"] = ra
         print(f"[bench] adjoint {wa.name}: forward {ra['forward_s']:.3f} s, backward {ra['backward_s']:.3f} s",
+              file=sys.stderr, flush=True)
+    if not args.no_rest_frame:
+        forms["rest_frame_collision_point"] = run_rest_frame(w)
+        r = forms["rest_frame_collision_point"]["rows"][-1]
+        print(f"[bench] rest frame at z_c: tau {r['tau']:.0f}, eps_loc tau {r['eps_loc_tau']:.3e}, "
+              f"2pT/eps_loc {r['2pT_over_eps_loc']:.3f}, pL/eps_loc {r['pL_over_eps_loc']:.3f}",
               file=sys.stderr, flush=True)
     if args.precision_study:
         wp = synth.PRECISION_SU3

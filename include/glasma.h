@@ -149,6 +149,18 @@ int glasma_deposit_current(glasma_ctx* ctx, void* j_out);
  * change the state.  Asynchronous. */
 int glasma_observe(glasma_ctx* ctx, double* d_out);
 
+/* Local rest frame of every layer (Sec. 4: the local energy density from diagonalising
+ * the energy-momentum tensor).  Reads the slices that glasma_observe wrote to d_obs
+ * (device, 4 * nz + GLASMA_OBS_NSCALARS doubles) and writes to d_out (device, 2 * nz
+ * doubles, caller-owned): eps_loc[z], the eigenvalue of the timelike eigenvector of the
+ * (t, z) block [[eps, -S_L], [S_L, -p_L]] of T^mu_nu, then v[z], that eigenvector's
+ * velocity along +z:
+ *   eps_loc = ((eps - p_L) + sqrt((eps + p_L)^2 - 4 S_L^2)) / 2,
+ *   v = 2 S_L / ((eps + p_L) + sqrt((eps + p_L)^2 - 4 S_L^2))
+ * (the square root of a negative round-off is taken as 0; v = 0 where eps + p_L = 0).
+ * Asynchronous on the context's stream; GLASMA_E_ARG for NULL pointers. */
+int glasma_rest_frame(glasma_ctx* ctx, const double* d_obs, double* d_out);
+
 /* Synchronous variant to host memory: tmunu_z [4][nz] (may be NULL) and scalars
  * (each may be NULL). */
 int glasma_observables(glasma_ctx* ctx, double* tmunu_z, double* gauss_rel, double* gauss_max,

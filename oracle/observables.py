@@ -13,7 +13,7 @@ E = d_t A is minus the physical electric field, hence the overall sign of S_L, w
 makes a +z mover carry S_L > 0 (checked on a single nucleus).  All quantities sit at
 the base site x of their link / plaquette.  Slices are transverse means at each n_z.
 
-Pinned by tests/test_oracle_observables.py: energy conservation in free evolution,
+Pinned by tests/test_oracle_lattice.py and tests/test_oracle_init.py: energy conservation in free evolution,
 gauge invariance, a single nucleus before the collision (p_T ~ 0, p_L ~ eps,
 S_L ~ +/- eps), and an abelian plane wave with closed-form energy density.
 """
@@ -70,3 +70,33 @@ def observables(st, E_new=None):
     g_rel, g_max = gauss_residual(st)
     return {"tmunu_z": slices, "energy": H, "gauss_rel": g_rel, "gauss_max": g_max,
             "unitarity": unitarity_violation(st.U)}
+
+
+def local_rest_frame(slices):
+    """Local rest frame energy density and flow velocity per z slice (Sec. 4: diagonalising
+    the energy-momentum tensor gives eps_loc).
+
+    From the transverse means T^00 = eps, T^0z = T^z0 = S_L (momentum density along +z) and
+    T^zz = p_L the (t, z) block of T^mu_nu = T^{mu rho} g_{rho nu}, g = diag(1, -1), is
+    [[eps, -S_L], [S_L, -p_L]].  Its timelike eigenvector u = gamma (1, v) solves
+    S_L v^2 - (eps + p_L) v + S_L = 0, the root with |v| < 1 being
+        v = 2 S_L / ((eps + p_L) + sqrt((eps + p_L)^2 - 4 S_L^2)),
+    and the eigenvalue eps_loc = eps - S_L v = ((eps - p_L) + sqrt((eps + p_L)^2 - 4 S_L^2)) / 2.
+    (The transverse block is already diagonal after the transverse average.)
+    slices: (4, Nz) = [eps, p_L, p_T, S_L].  Returns (eps_loc, v), each (Nz,)."""
+    eps, pL, _, SL = (np.asarray(slices[k], dtype=np.float64) for k in range(4))
+    s = eps + pL
+    root = np.sqrt(np.maximum(s * s - 4.0 * SL * SL, 0.0))
+    den = s + root
+    v = np.where(den > 0, 2.0 * SL / np.where(den > 0, den, 1.0), 0.0)
+    return eps - SL * v, v
+
+
+def milne(t, z, t_c, z_c):
+    """Proper time and space-time rapidity of (t, z) relative to the collision point
+    (t_c, z_c): tau = sqrt(dt^2 - dz^2), eta_s = atanh(dz / dt) for |dz| < dt (Sec. 4)."""
+    dt, dz = np.asarray(t, dtype=np.float64) - t_c, np.asarray(z, dtype=np.float64) - z_c
+    inside = np.abs(dz) < dt
+    tau = np.where(inside, np.sqrt(np.where(inside, dt * dt - dz * dz, 0.0)), np.nan)
+    eta = np.where(inside, np.arctanh(np.where(inside, dz / np.where(dt != 0, dt, 1.0), 0.0)), np.nan)
+    return tau, eta

@@ -411,6 +411,13 @@ int glasma_observe(glasma_ctx* c, double* d_out) {
   return GLASMA_OK;
 }
 
+int glasma_rest_frame(glasma_ctx* c, const double* d_obs, double* d_out) {
+  if (!c || !d_obs || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
+  launch_rest_frame(d_obs, c->g.nz, d_out, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
 int glasma_observables(glasma_ctx* c, double* tmunu_z, double* gauss_rel, double* gauss_max, double* energy,
                        double* unitarity_max) {
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");

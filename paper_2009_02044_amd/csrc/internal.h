@@ -46,6 +46,8 @@ template <typename G, typename T>
 void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
                     const StepConst& c, double* partial, double* out, hipStream_t st);
 size_t observe_partial_doubles(const Geom& g);
+// local rest frame per layer from the observe slices (2 * nz doubles out)
+void launch_rest_frame(const double* obs, int nz, double* out, hipStream_t st);
 
 template <typename G, typename T>
 void launch_current(const T* U, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c,

@@ -225,6 +225,24 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 
+// ---- local rest frame per layer (Sec. 4) ----------------------------------------
+// eps_loc and the frame velocity v along +z from the timelike eigenvector of the (t, z)
+// block of T^mu_nu, [[eps, -S_L], [S_L, -p_L]]:  S_L v^2 - (eps + p_L) v + S_L = 0.
+__global__ void k_rest_frame(const double* __restrict__ obs, int nz, double* __restrict__ out) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  const double eps = obs[z], pL = obs[nz + z], SL = obs[3 * nz + z];
+  const double s = eps + pL;
+  const double root = sqrt(fmax(s * s - 4.0 * SL * SL, 0.0));
+  const double den = s + root;
+  const double v = den > 0.0 ? 2.0 * SL / den : 0.0;
+  out[z] = eps - SL * v;
+  out[nz + z] = v;
+}
+void launch_rest_frame(const double* obs, int nz, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rest_frame, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, obs, nz, out);
+}
+
 // ---- current of the next step (tests) --------------------------------------
 template <typename G, typename T>
 __global__ void k_current(const T* __restrict__ U, const T* __restrict__ rhoA, const T* __restrict__ rhoB,

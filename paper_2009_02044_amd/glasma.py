@@ -117,6 +117,13 @@ class Lattice:
         """Asynchronous: write slices + scalars into the float64 device tensor `out`."""
         self._chk(lib.glasma_observe(self.ctx, C.c_void_p(out.data_ptr())))
 
+    def rest_frame(self, obs):
+        """Local rest frame of every layer from an observe() buffer (glasma_rest_frame):
+        device float64 tensor (2, nz) = [eps_loc, v]."""
+        out = torch.empty(2, self.nz, dtype=torch.float64, device=self.device)
+        self._chk(lib.glasma_rest_frame(self.ctx, C.c_void_p(obs.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
     def observables(self):
         t = np.empty((4, self.nz))
         vals = [C.c_double() for _ in range(4)]

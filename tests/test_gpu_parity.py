@@ -251,3 +251,32 @@ def test_leapfrog_generic_state_row_layouts(nc, nz, nt):
     go, oo = lat.observables(), observables.observables(st)
     _obs_close(go, oo, 1e-10)
     assert go["gauss_rel"] < 1e-12
+
+
+def test_rest_frame_against_oracle():
+    """Local rest frame per layer (glasma_rest_frame on the observe slices) against the
+    oracle's eps_loc and frame velocity from its own slices, two colliding nuclei mid-way
+    through their overlap."""
+    pkg = lattice_or_skip()
+    import torch
+    w = synth.Workload("su2-64x8x8", nc=2, nz=64, nt=8, mu=1.0, sigma=4.0, seed=1001)
+    say("case: rest frame su2 64x8x8")
+    p, mv = mv_setup(w)
+    rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+    st, _ = init_mv.initial_state(rA, rB, w.nz, p, mv)
+    lat = new_lattice(pkg, w)
+    lat.init_state(*to_comp(st), step0=0)
+    n = 30
+    st = lattice.evolve(st, n)
+    lat.step(n)
+    obs = lat.obs_buffer()
+    lat.observe(obs)
+    got = lat.rest_frame(obs)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    el, v = observables.local_rest_frame(observables.tmunu_slices(st)[0])
+    scale = np.abs(observables.tmunu_slices(st)[0][0]).max()
+    assert np.max(np.abs(got[0] - el)) < 1e-8 * scale, np.max(np.abs(got[0] - el)) / scale
+    big = np.abs(el) > 1e-3 * scale
+    assert np.max(np.abs(got[1] - v)[big]) < 1e-6
+    assert np.all(np.abs(got[1]) < 1.0)
