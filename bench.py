@@ -5,7 +5,7 @@ SU(3), a_T = 4 a_L, dt = a_L/2, two MV nuclei (mu = 0.5, sigma = 8 a_L, m = 0.2,
 Lambda = 10/a_T), initial state built on the GPU.  One step = one leapfrog update of
 every link and E field with the CPIC charge hop on every second step; observables
 (T^{mu nu} slices, Gauss residual, energy) are reduced every 16 steps inside the
-timed region.  Inputs are resident in HBM before timing starts.
+timed region (by the observing step: glasma_step_observe).  Inputs are resident in HBM before timing starts.
 
 The JSON line reports site-updates/s of the FP64 single-event form (value), the
 roofline of its dominant kernel (the fused leapfrog step, timed with HIP events on
@@ -90,10 +90,11 @@ def run_plain(w, fp, steps, warmup, obs_every=16, scheme=0, tol=1e-12):
             for _ in range(n):
                 lat.step(1)
                 iters.append(lat.last_iterations)
+            lat.observe(obs)
         else:
-            lat.step(n)
+            # the last step of each chunk also reduces the observables (glasma_step_observe)
+            lat.step_observe(n, obs)
         done += n
-        lat.observe(obs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,

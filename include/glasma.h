@@ -149,6 +149,16 @@ int glasma_deposit_current(glasma_ctx* ctx, void* j_out);
  * change the state.  Asynchronous. */
 int glasma_observe(glasma_ctx* ctx, double* d_out);
 
+/* n >= 1 steps, writing to d_out (device, as glasma_observe) the observables of the state
+ * the last step starts from: the same as glasma_step(n - 1), glasma_observe,
+ * glasma_step(1), up to rounding.  For the FP64 leapfrog with nt a multiple of 64 the last
+ * step computes them on the way (a Gauss-residual pass over the state before it, the
+ * energy slots inside the step kernel, which has the forces and plaquettes at hand), at a
+ * fraction of a separate glasma_observe; otherwise it runs exactly that sequence.  The
+ * non-finite slot then counts detections (a site may count twice).  Asynchronous; errors
+ * as glasma_step. */
+int glasma_step_observe(glasma_ctx* ctx, int32_t n, double* d_out);
+
 /* Local rest frame of every layer (Sec. 4: the local energy density from diagonalising
  * the energy-momentum tensor).  Reads the slices that glasma_observe wrote to d_obs
  * (device, 4 * nz + GLASMA_OBS_NSCALARS doubles) and writes to d_out (device, 2 * nz

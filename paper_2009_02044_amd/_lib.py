@@ -59,6 +59,7 @@ def _load():
         "glasma_deposit_current": ([P, V], C.c_int),
         "glasma_observe": ([P, V], C.c_int),
         "glasma_rest_frame": ([P, V, V], C.c_int),
+        "glasma_step_observe": ([P, I32, V], C.c_int),
         "glasma_observables": ([P, D, D, D, D, D], C.c_int),
         "glasma_get_state": ([P, D, D, D, D, C.POINTER(I64)], C.c_int),
         "glasma_reunitarize": ([P], C.c_int),

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <cstdio>
 #include <cmath>
+#include <type_traits>
 #include "internal.h"
 #include "adjoint.h"
 #include "../../include/glasma.h"
@@ -343,34 +344,68 @@ int glasma_step(glasma_ctx* c, int32_t n) {
   return advance(c, n);
 }
 
-static int advance(glasma_ctx* c, int32_t n) {
-  for (int32_t k = 0; k < n; ++k) {
-    StepConst sc = step_const(c);
-    if (c->p.scheme == 1) {
-      int rc = semi_step(c, sc);
-      if (rc) return rc;
-    } else {
-      dispatch(c, [&]<typename G, typename T>() -> int {
-        launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
-                              c->stream);
-        return 0;
-      });
-    }
-    c->cur ^= 1;
-    if (sc.hop) {
-      c->offA = (c->offA + 1) % c->g.nz;
-      c->offB = (c->offB + 1) % c->g.nz;
-    }
-    c->step += 1;
-    if (c->p.reunit_every > 0 && c->step % c->p.reunit_every == 0) {
-      dispatch(c, [&]<typename G, typename T>() -> int {
-        launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
-        return 0;
-      });
-    }
+// One step; with d_obs (the observing step: FP64 leapfrog, nt a multiple of 64) it also
+// writes to d_obs the observables of the state it starts from, the Gauss residual kernel
+// running first on that state and the step kernel adding the energy slots.
+static int one_step(glasma_ctx* c, double* d_obs) {
+  StepConst sc = step_const(c);
+  if (c->p.scheme == 1) {
+    int rc = semi_step(c, sc);
+    if (rc) return rc;
+  } else if (d_obs) {
+    double* partial = (double*)c->b.work;
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      if constexpr (std::is_same_v<T, double>) {
+        launch_obs_gauss<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, partial,
+                               c->stream);
+        launch_leapfrog_observe<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g,
+                                      sc, partial, c->stream);
+      }
+      return 0;
+    });
+    launch_observe_finish(partial, fused_observe_blocks_per_layer(c->g), c->g, sc, d_obs, c->stream);
+  } else {
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
+                            c->stream);
+      return 0;
+    });
+  }
+  c->cur ^= 1;
+  if (sc.hop) {
+    c->offA = (c->offA + 1) % c->g.nz;
+    c->offB = (c->offB + 1) % c->g.nz;
+  }
+  c->step += 1;
+  if (c->p.reunit_every > 0 && c->step % c->p.reunit_every == 0) {
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
+      return 0;
+    });
   }
   HIPCHK(c, hipGetLastError());
   return GLASMA_OK;
+}
+
+static int advance(glasma_ctx* c, int32_t n) {
+  for (int32_t k = 0; k < n; ++k) {
+    int rc = one_step(c, nullptr);
+    if (rc) return rc;
+  }
+  return GLASMA_OK;
+}
+
+int glasma_step_observe(glasma_ctx* c, int32_t n, double* d_out) {
+  if (!c || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (n < 1) return fail(c, GLASMA_E_ARG, "n must be >= 1");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state: call glasma_init_state or glasma_init_mv first");
+  c->adj_ok = false;
+  int rc = advance(c, n - 1);
+  if (rc) return rc;
+  if (c->p.fp == 64 && c->p.scheme == 0 && fused_observe_geometry(c->g)) return one_step(c, d_out);
+  rc = glasma_observe(c, d_out);
+  if (rc) return rc;
+  return advance(c, 1);
 }
 
 int glasma_reunitarize(glasma_ctx* c) {

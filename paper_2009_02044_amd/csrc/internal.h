@@ -46,6 +46,18 @@ template <typename G, typename T>
 void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
                     const StepConst& c, double* partial, double* out, hipStream_t st);
 size_t observe_partial_doubles(const Geom& g);
+// Observing step (FP64 leapfrog, nt a multiple of 64): the Gauss residual kernel runs on
+// the state before the step, the step kernel adds the energy slots, then the finish pass.
+bool fused_observe_geometry(const Geom& g);
+int fused_observe_blocks_per_layer(const Geom& g);
+template <typename G, typename T>
+void launch_obs_gauss(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c,
+                      double* partial, hipStream_t st);
+template <typename G, typename T>
+void launch_leapfrog_observe(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
+                             double* partial, hipStream_t st);
+void launch_observe_finish(const double* partial, int nbx, const Geom& g, const StepConst& c, double* out,
+                           hipStream_t st);
 // local rest frame per layer from the observe slices (2 * nz doubles out)
 void launch_rest_frame(const double* obs, int nz, double* out, hipStream_t st);
 

@@ -14,10 +14,10 @@
 // order, so results are bitwise reproducible.
 #include "internal.h"
 #include "stencil.h"
+#include "reduce.h"
 
 namespace gl {
 
-constexpr int NQ = 9;   // eps, pL, pT, SL, |G|^2, |rho|^2, max|G^a|, max unitarity, nonfinite
 constexpr int OBS_BS = 256;
 #ifndef GL_OBS_OWN
 #define GL_OBS_OWN OWN_LDS
@@ -29,22 +29,6 @@ size_t observe_partial_doubles(const Geom& g) {
   return (size_t)obs_blocks_per_layer(g) * g.nz * NQ;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  return v;
-}
-
-template <typename A> __device__ __forceinline__ double norm2(const A& a) {
-  constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
-  double s = 0;
-#pragma unroll
-  for (int k = 0; k < NG; ++k) s += (double)a.c[k] * (double)a.c[k];
-  return s;
-}
 
 template <typename G, typename T, bool XS>
 __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, const T* __restrict__ E,
@@ -155,21 +139,57 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     bad |= !isfinite(acc[0]) || !isfinite(acc[4]);
     acc[8] += bad ? 1.0 : 0.0;
   }
-  // block reduction: 64-lane shuffles, then across the waves through LDS
-  __shared__ double red[OBS_BS / 64][NQ];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  block_reduce_write<OBS_BS>(acc, Q_ALL, partial + ((int64_t)z * nbx + blockIdx.x) * NQ);
+}
+
+// Gauss residual, |rho| and the non-finite count over the step kernel's work-groups (column
+// map), for the observing step: it runs before that step, which then adds the energy
+// slots to the same partial sums.  G(x) = sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)]/a_i
+// - rho(x) at (U(t), E(t - dt/2), rho(t - dt/2)).  Partial slot of block b: z nbx + col.
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, const T* __restrict__ E,
+                                                   const T* __restrict__ rhoA, const T* __restrict__ rhoB,
+                                                   Geom g, StepConst c, ColMap m, double* __restrict__ partial,
+                                                   int nbx) {
+  using L = typename G::Link;
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t Vp = g.Vp;
+  Site x;
+  uint32_t s;
+  const bool has = col_map_site(g, m, blockIdx.x, threadIdx.x, blockDim.x, x, s);
+  double acc[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double v = (q == 6 || q == 7) ? wave_max(acc[q]) : wave_sum(acc[q]);
-    if (lane == 0) red[wv][q] = v;
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (has) {
+    A G_, r, rb;
+    load_alg(r, rhoA, 0, site_index(g, x.x, x.y, slotA(x.z, c.offA, g.nz)), Vp);
+    load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz)), Vp);
+    for (int k = 0; k < NG; ++k) { r.c[k] += rb.c[k]; G_.c[k] = -r.c[k]; }
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
+      const uint32_t sm = idx(g, shifted(g, x, i, -1));
+      L Um;
+      load_link(Um, U, i, sm, Vp);
+      A eh, em;
+      load_alg(eh, E, i, s, Vp);
+      load_alg(em, E, i, sm, Vp);
+      const A tr = G::transport(Um, em);
+      for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tr.c[k]) / ai;
+    }
+    acc[Q_G2] = norm2(G_);
+    acc[Q_RHO2] = norm2(r);
+    double gm = 0.0;
+    for (int k = 0; k < NG; ++k) gm = fmax(gm, fabs(G_.c[k]));
+    acc[Q_GMAX] = gm;
+    acc[Q_BAD] = isfinite(acc[Q_G2]) ? 0.0 : 1.0;
   }
-  __syncthreads();
-  if (threadIdx.x < NQ) {
-    const int q = threadIdx.x;
-    double v = red[0][q];
-    for (int w = 1; w < OBS_BS / 64; ++w) v = (q == 6 || q == 7) ? fmax(v, red[w][q]) : v + red[w][q];
-    partial[((int64_t)z * nbx + blockIdx.x) * NQ + q] = v;
-  }
+  const int k = (int)(blockIdx.x % NXCD);
+  const uint32_t j = blockIdx.x / NXCD;
+  const uint32_t z = j / (uint32_t)m.bt, ch = j % (uint32_t)m.bt;
+  const unsigned mask = (1u << Q_G2) | (1u << Q_RHO2) | (1u << Q_GMAX) | (1u << Q_BAD);
+  block_reduce_write<256>(acc, mask, partial + ((int64_t)z * nbx + (int64_t)k * m.bt + ch) * NQ);
 }
 
 __global__ void __launch_bounds__(256) k_observe_finish(const double* __restrict__ partial, int nbx, Geom g,
@@ -222,6 +242,22 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
     hipLaunchKernelGGL((k_observe<Gd, T, true>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
   else
     hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+  hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
+}
+
+// ---- pieces of the observing step (nt a multiple of 64: full column-map blocks) ----
+bool fused_observe_geometry(const Geom& g) { return g.nt % 64 == 0; }
+int fused_observe_blocks_per_layer(const Geom& g) { return NXCD * col_map(g, 256).bt; }
+template <typename G, typename T>
+void launch_obs_gauss(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c,
+                      double* partial, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const ColMap m = col_map(g, 256);
+  hipLaunchKernelGGL((k_obs_gauss<Gd, T>), dim3(col_map_blocks(g, m)), dim3(256), 0, st, U, E, rhoA, rhoB, g, c, m,
+                     partial, fused_observe_blocks_per_layer(g));
+}
+void launch_observe_finish(const double* partial, int nbx, const Geom& g, const StepConst& c, double* out,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 
@@ -307,7 +343,9 @@ void launch_reunit(T* U, const Geom& g, hipStream_t st) {
                                      double*, double*, hipStream_t);                                        \
   template void launch_current<G, T>(const T*, const T*, const T*, const Geom&, const StepConst&, T*,      \
                                      hipStream_t);                                                          \
-  template void launch_reunit<G, T>(T*, const Geom&, hipStream_t);
+  template void launch_reunit<G, T>(T*, const Geom&, hipStream_t);                                        \
+  template void launch_obs_gauss<G, T>(const T*, const T*, const T*, const T*, const Geom&, const StepConst&, \
+                                       double*, hipStream_t);
 GL_INST(Su2<double>, double)
 GL_INST(Su3<double>, double)
 GL_INST(Su2<float>, float)

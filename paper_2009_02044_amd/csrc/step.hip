@@ -15,6 +15,7 @@
 // With co-moving charge storage both rewrites are in place (one slot per thread).
 #include "internal.h"
 #include "stencil.h"
+#include "reduce.h"
 
 namespace gl {
 
@@ -33,13 +34,22 @@ template <typename R> __device__ __forceinline__ Q2<double> to_double(const Q2<R
   return r;
 }
 
+// Observables gathered by an observing step (FP64): the E and B parts of T^{mu nu} at the
+// integer time of the state the step starts from (E averaged over the two half steps,
+// B from the forward plaquettes), the worst link unitarity and a non-finite flag.
+template <typename G> struct ObsAcc {
+  double EL2 = 0.0, ET2 = 0.0, sl = 0.0, uv = 0.0;
+  bool bad = false;
+  PlaqObs<G> pl;
+};
+
 // Update of link (x, i) from the force term f_i of plaquette_forces (F_i = -f_i / a_i);
 // the z-link thread also hops the charges.
-template <typename G, typename T, bool HOP>
+template <typename G, typename T, bool HOP, bool OBS = false>
 __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const typename G::Alg& fi,
                                             T* __restrict__ Unew, T* __restrict__ E, T* __restrict__ rhoA,
                                             T* __restrict__ rhoB, const Geom& g, const StepConst& c, Site x,
-                                            uint32_t s, int i, bool reunit) {
+                                            uint32_t s, int i, bool reunit, ObsAcc<G>* oa = nullptr) {
   using L = typename G::Link;
   using A = typename G::Alg;
   constexpr int NG = G::NG;
@@ -48,6 +58,8 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
   const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
   A e;
   load_alg(e, E, i, s, Vp);
+  A eo;
+  if constexpr (OBS) eo = e;
   const T kf = (T)(-c.dt / ai);
 #pragma unroll
   for (int k = 0; k < NG; ++k) e.c[k] = fmx(kf, fi.c[k], e.c[k]);
@@ -67,6 +79,23 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
     for (int k = 0; k < NG; ++k) e.c[k] += al * (ran.c[k] - rb.c[k]);
   }
   store_alg(e, E, i, s, Vp);
+  if constexpr (OBS) {
+    // E^2 averaged over the half steps; S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x)
+    //                                             + Ebar_y^a P(U_yz)^a / (a_y a_z))
+    const double e2 = 0.5 * (norm2(eo) + norm2(e));
+    if (i == 2) oa->EL2 = e2; else oa->ET2 += e2;
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const double pk = i == 0 ? oa->pl.p[1].c[k] : oa->pl.p[2].c[k];
+      d += 0.5 * ((double)eo.c[k] + (double)e.c[k]) * pk;
+      oa->bad |= !isfinite((double)e.c[k]);
+    }
+    if (i < 2) oa->sl += d / (c.a[2] * ai);
+    const double uv = (double)G::unit_violation(Ui);
+    oa->bad |= !isfinite(uv);
+    oa->uv = fmax(oa->uv, uv);
+  }
   L Un = G::template expi_mul<true>(e, (T)(ai * c.dt), Ui);
   if (reunit) {
     // projection back onto SU(N) in double arithmetic
@@ -78,16 +107,18 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
 }
 
 // The whole site update from plaquette forces.
-template <typename G, typename T, bool HOP, bool XS, int OWN>
+template <typename G, typename T, bool HOP, bool XS, int OWN, bool OBS = false>
 __device__ __forceinline__ void update_site(const T* __restrict__ U, T* __restrict__ Unew, T* __restrict__ E,
                                             T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
                                             const StepConst& c, const double* inv_a2, Site x, uint32_t s,
-                                            bool reunit, typename Vec16<T>::type* slot, uint32_t TB) {
+                                            bool reunit, typename Vec16<T>::type* slot, uint32_t TB,
+                                            ObsAcc<G>* oa = nullptr) {
   using L = typename G::Link;
   const GlobalLinks<T> fetch{U, g.Vp};
   const OwnLinks<G, T, OWN> own(fetch, s, slot, threadIdx.x, TB);
   typename G::Alg f[3];
-  plaquette_forces<G, XS>(fetch, own, g, x, inv_a2, f);
+  if constexpr (OBS) plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &oa->pl);
+  else plaquette_forces<G, XS>(fetch, own, g, x, inv_a2, f);
 #pragma unroll 1
   for (int i = 0; i < 3; ++i) {
     L Ui;
@@ -95,7 +126,7 @@ __device__ __forceinline__ void update_site(const T* __restrict__ U, T* __restri
     typename G::Alg fi;
 #pragma unroll
     for (int k = 0; k < G::NG; ++k) fi.c[k] = i == 0 ? f[0].c[k] : (i == 1 ? f[1].c[k] : f[2].c[k]);
-    finish_link<G, T, HOP>(Ui, fi, Unew, E, rhoA, rhoB, g, c, x, s, i, reunit);
+    finish_link<G, T, HOP, OBS>(Ui, fi, Unew, E, rhoA, rhoB, g, c, x, s, i, reunit, oa);
   }
 }
 
@@ -118,17 +149,45 @@ template <typename G, typename T, int TB> struct OwnLds {
 #endif
 // One thread per site, the three directions in turn.
 constexpr int LF_BS = 256;
-template <typename G, typename T, bool HOP, bool XS>
+// OBS: also gather the observables of the state the step starts from into the partial
+// sums of this work-group (full work-groups only: every thread reaches the reduction).
+template <typename G, typename T, bool HOP, bool XS, bool OBS = false>
 __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
                                                                  T* __restrict__ E, T* __restrict__ rhoA,
                                                                  T* __restrict__ rhoB, Geom g, StepConst c,
-                                                                 ColMap m) {
+                                                                 ColMap m, double* __restrict__ partial = nullptr) {
   Site x;
   uint32_t s;
   __shared__ typename Vec16<T>::type slot[OwnLds<G, T, LF_BS>::N];
   if (!col_map_site(g, m, blockIdx.x, threadIdx.x, LF_BS, x, s)) return;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
-  update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
+  if constexpr (!OBS) {
+    update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
+  } else {
+    ObsAcc<G> oa;
+    update_site<G, T, HOP, XS, OwnMode<G, T>::value, true>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot,
+                                                           LF_BS, &oa);
+    // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) from the forward plaquettes (U_{z,x} = U_{x,z}^dag)
+    const double nc = (double)G::NC;
+    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - oa.pl.tr[0]);
+    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - oa.pl.tr[2]);
+    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - oa.pl.tr[1]);
+    const double BL2 = bxy, BT2 = byz + bzx;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    acc[Q_EPS] = 0.5 * (oa.EL2 + oa.ET2 + BL2 + BT2);
+    acc[Q_PL] = 0.5 * (oa.ET2 + BT2 - oa.EL2 - BL2);
+    acc[Q_PT] = 0.5 * (oa.EL2 + BL2);
+    acc[Q_SL] = oa.sl;
+    acc[Q_UNIT] = oa.uv;
+    acc[Q_BAD] = (oa.bad || !isfinite(acc[Q_EPS])) ? 1.0 : 0.0;
+    const int k = (int)(blockIdx.x % NXCD);
+    const uint32_t j = blockIdx.x / NXCD;
+    const uint32_t col = (uint32_t)k * m.bt + j % (uint32_t)m.bt;
+    const unsigned mask = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_UNIT) | (1u << Q_BAD);
+    block_reduce_write<LF_BS, true>(acc, mask, partial + ((int64_t)x.z * NXCD * m.bt + col) * NQ);
+  }
 }
 
 template <typename G, typename T>
@@ -147,6 +206,27 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
     else hipLaunchKernelGGL((k_leapfrog<G, T, false, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
   }
 }
+
+// The observing step: the leapfrog step that also writes the energy slots of the
+// observables of the state it starts from (FP64; nt a multiple of 64, so the column map
+// has only full work-groups and every row lies in a wavefront).
+template <typename G, typename T>
+void launch_leapfrog_observe(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
+                             double* partial, hipStream_t st) {
+  const int bs = LF_BS;
+  const ColMap m = col_map(g, bs);
+  const unsigned nbc = col_map_blocks(g, m);
+  if (c.hop)
+    hipLaunchKernelGGL((k_leapfrog<G, T, true, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g,
+                       c, m, partial);
+  else
+    hipLaunchKernelGGL((k_leapfrog<G, T, false, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g,
+                       c, m, partial);
+}
+template void launch_leapfrog_observe<Su3<double>, double>(const double*, double*, double*, double*, double*,
+                                                          const Geom&, const StepConst&, double*, hipStream_t);
+template void launch_leapfrog_observe<Su2<double>, double>(const double*, double*, double*, double*, double*,
+                                                          const Geom&, const StepConst&, double*, hipStream_t);
 
 // ---- batched form: many events of different sizes in one launch --------------
 

@@ -117,6 +117,11 @@ class Lattice:
         """Asynchronous: write slices + scalars into the float64 device tensor `out`."""
         self._chk(lib.glasma_observe(self.ctx, C.c_void_p(out.data_ptr())))
 
+    def step_observe(self, n, out):
+        """n >= 1 steps; `out` (an obs_buffer()) receives the observables of the state the
+        last step starts from (glasma_step_observe).  Asynchronous."""
+        self._chk(lib.glasma_step_observe(self.ctx, int(n), C.c_void_p(out.data_ptr())))
+
     def rest_frame(self, obs):
         """Local rest frame of every layer from an observe() buffer (glasma_rest_frame):
         device float64 tensor (2, nz) = [eps_loc, v]."""

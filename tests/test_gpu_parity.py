@@ -280,3 +280,44 @@ def test_rest_frame_against_oracle():
     big = np.abs(el) > 1e-3 * scale
     assert np.max(np.abs(got[1] - v)[big]) < 1e-6
     assert np.all(np.abs(got[1]) < 1.0)
+
+
+@pytest.mark.parametrize("nc,nz,nt,fp", [(3, 4, 64, 64), (2, 4, 64, 64), (3, 6, 8, 64), (3, 4, 64, 32)])
+def test_step_observe_equals_step_then_observe(nc, nz, nt, fp):
+    """glasma_step_observe(n) against glasma_step(n - 1), glasma_observe, glasma_step(1):
+    the same observables (the FP64 nt = 64 cases take the observing step: Gauss pass plus
+    energy slots inside the step kernel) and the same final state."""
+    pkg = lattice_or_skip()
+    import torch
+    say(f"case: step_observe su{nc} {nz}x{nt}x{nt} fp{fp}")
+    dims = (nz, nt, nt)
+    ng = nc * nc - 1
+    p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=0.5)
+    st = init_mv.state_from_algebra(synth.normal(400 + nt, (3,) + dims + (ng,), 0.6),
+                                    synth.normal(500 + nt, (3,) + dims + (ng,), 0.3), p)
+    st.rhoA = st.rhoA * 1.001          # a non-trivial Gauss residual
+    comp = to_comp(st)
+    a = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=0.5, fp=fp)
+    b = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=0.5, fp=fp)
+    a.init_state(*comp, step0=0)
+    b.init_state(*comp, step0=0)
+    oa, ob = a.obs_buffer(), b.obs_buffer()
+    n = 5
+    a.step_observe(n, oa)
+    b.step(n - 1)
+    b.observe(ob)
+    b.step(1)
+    torch.cuda.synchronize()
+    ga, gb = pkg.Lattice.unpack_obs(oa, nz), pkg.Lattice.unpack_obs(ob, nz)
+    sc = np.abs(gb["tmunu_z"]).max(axis=1, keepdims=True)
+    tol = 1e-11 if fp == 64 else 1e-5
+    assert np.max(np.abs(ga["tmunu_z"] - gb["tmunu_z"]) / sc) < tol
+    assert abs(ga["energy"] - gb["energy"]) < tol * abs(gb["energy"])
+    for k in ("gauss_l2", "rho_l2", "gauss_max"):
+        if k in gb:
+            assert abs(ga[k] - gb[k]) <= 1e-9 * abs(gb[k]) + 1e-14, (k, ga[k], gb[k])
+    assert abs(ga["unitarity"] - gb["unitarity"]) < 1e-12 + 1e-6 * (fp == 32)
+    assert ga["nonfinite"] == 0 and gb["nonfinite"] == 0
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("U", "E", "rhoA", "rhoB"):
+        assert np.array_equal(sa[k], sb[k]), k
