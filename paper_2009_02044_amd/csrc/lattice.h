@@ -239,36 +239,80 @@ GL_HD uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + (x < r ? x : r) + b / NXCD;
 }
 
-// Column decomposition of the lattice over the XCDs: XCD k owns a contiguous range of
-// transverse rows y for every z and sweeps it layer by layer, so the links a block
-// loads as z + 1 neighbours are read again, as z and z - 1, by the blocks that follow
-// on the same XCD while they are still in its L2; rows are x-contiguous, so only the
-// y halo of the row range crosses XCDs.  Work-group b runs on XCD b mod 8 and covers
-// BS consecutive sites of one (z, row range) segment; blocks past a segment's end idle.
+// Placement of the step's work-groups on the XCDs (work-group b runs on XCD b mod 8,
+// each XCD has its own L2).  Two decompositions:
+//  * rows: XCD k owns a contiguous range of transverse rows y of every layer and sweeps
+//    the layers in order, so the links a block loads as z + 1 neighbours are read again,
+//    as z and z - 1, by the blocks that follow on the same XCD; the y halo of the row
+//    range crosses XCDs on every layer.
+//  * slabs: XCD k owns a contiguous range of layers z, whole, and sweeps them in order;
+//    only the two end layers of a slab cross XCDs.
+// A block covers BS consecutive sites of one (z, segment) pair, segment = the XCD's row
+// range (rows) or the whole layer (slabs); blocks past a segment's end idle.  Slabs are
+// the default: with the -z plaquettes taken first (so that a block reads its z - 1
+// links while the blocks of that layer read them as their own) the step kernel fetches
+// 17% fewer HBM bytes than with rows, at the same speed.
+#ifndef GL_ZSLAB
+#define GL_ZSLAB 1
+#endif
 struct ColMap {
-  int r0, rem;   // rows per XCD: r0 + (k < rem)
-  int bt;        // blocks per (XCD, layer)
+  int r0, rem;   // rows (rows) or layers (slabs) per XCD: r0 + (k < rem)
+  int bt;        // blocks per (XCD, layer) (rows) or per layer (slabs)
+  int slab;      // 1: slab decomposition
 };
-inline ColMap col_map(const Geom& g, int bs) {
+inline ColMap col_map(const Geom& g, int bs, int slab = GL_ZSLAB) {
   ColMap m;
-  m.r0 = g.nt / NXCD;
-  m.rem = g.nt % NXCD;
-  const int64_t maxrows = m.r0 + (m.rem > 0 ? 1 : 0);
-  m.bt = (int)((maxrows * g.nt + bs - 1) / bs);
+  m.slab = slab;
+  const int n = slab ? g.nz : g.nt;
+  m.r0 = n / NXCD;
+  m.rem = n % NXCD;
+  const int64_t seg = slab ? (int64_t)g.layer : (int64_t)(m.r0 + (m.rem > 0 ? 1 : 0)) * g.nt;
+  m.bt = (int)((seg + bs - 1) / bs);
   return m;
 }
-inline uint32_t col_map_blocks(const Geom& g, const ColMap& m) { return (uint32_t)NXCD * g.nz * m.bt; }
+inline uint32_t col_map_blocks(const Geom& g, const ColMap& m) {
+  const int64_t per = m.slab ? (int64_t)(m.r0 + (m.rem > 0 ? 1 : 0)) : (int64_t)g.nz;
+  return (uint32_t)(NXCD * per * m.bt);
+}
+// partial-sum slots per layer: one per block that covers sites of that layer
+GL_HD int col_map_slots_per_layer(const ColMap& m) { return m.slab ? m.bt : NXCD * m.bt; }
+// layer of block b (may be >= nz or past the XCD's slab for idle blocks) and its slot
+GL_HD void col_map_block(const ColMap& m, uint32_t b, int& z, uint32_t& slot) {
+  const int k = (int)(b % NXCD);
+  const uint32_t j = b / NXCD;
+  const uint32_t ch = j % (uint32_t)m.bt;
+  if (m.slab) {
+    const int zl = (int)(j / (uint32_t)m.bt);
+    const int nk = m.r0 + (k < m.rem ? 1 : 0);
+    z = zl < nk ? k * m.r0 + (k < m.rem ? k : m.rem) + zl : 0x7fffffff;
+    slot = ch;
+  } else {
+    z = (int)(j / (uint32_t)m.bt);
+    slot = (uint32_t)k * m.bt + ch;
+  }
+}
 // site of thread t in block b, or false when the thread has no site
 GL_HD bool col_map_site(const Geom& g, const ColMap& m, uint32_t b, uint32_t t, uint32_t bs, Site& x, uint32_t& s) {
   const int k = (int)(b % NXCD);
   const uint32_t j = b / NXCD;
-  const int z = (int)(j / (uint32_t)m.bt);
   const uint32_t ch = j % (uint32_t)m.bt;
-  const int nrows = m.r0 + (k < m.rem ? 1 : 0);
-  const int start = k * m.r0 + (k < m.rem ? k : m.rem);
   const uint32_t local = ch * bs + t;
-  if (z >= g.nz || local >= (uint32_t)nrows * (uint32_t)g.nt) return false;
-  x.y = start + (int)(local / (uint32_t)g.nt);
+  int z, y0;
+  uint32_t seg;
+  if (m.slab) {
+    const int zl = (int)(j / (uint32_t)m.bt);
+    const int nk = m.r0 + (k < m.rem ? 1 : 0);
+    if (zl >= nk) return false;
+    z = k * m.r0 + (k < m.rem ? k : m.rem) + zl;
+    y0 = 0;
+    seg = (uint32_t)g.layer;
+  } else {
+    z = (int)(j / (uint32_t)m.bt);
+    y0 = k * m.r0 + (k < m.rem ? k : m.rem);
+    seg = (uint32_t)(m.r0 + (k < m.rem ? 1 : 0)) * (uint32_t)g.nt;
+  }
+  if (z >= g.nz || local >= seg) return false;
+  x.y = y0 + (int)(local / (uint32_t)g.nt);
   x.x = (int)(local % (uint32_t)g.nt);
   x.z = z;
   s = site_index(g, x.x, x.y, x.z);

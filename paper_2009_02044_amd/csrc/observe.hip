@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
 // Gauss residual, |rho| and the non-finite count over the step kernel's work-groups (column
 // map), for the observing step: it runs before that step, which then adds the energy
 // slots to the same partial sums.  G(x) = sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)]/a_i
-// - rho(x) at (U(t), E(t - dt/2), rho(t - dt/2)).  Partial slot of block b: z nbx + col.
+// - rho(x) at (U(t), E(t - dt/2), rho(t - dt/2)).  Partial slot of block b: z nbx + its slot.
 template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, const T* __restrict__ E,
                                                    const T* __restrict__ rhoA, const T* __restrict__ rhoB,
@@ -185,11 +185,12 @@ __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, cons
     acc[Q_GMAX] = gm;
     acc[Q_BAD] = isfinite(acc[Q_G2]) ? 0.0 : 1.0;
   }
-  const int k = (int)(blockIdx.x % NXCD);
-  const uint32_t j = blockIdx.x / NXCD;
-  const uint32_t z = j / (uint32_t)m.bt, ch = j % (uint32_t)m.bt;
+  int z;
+  uint32_t slot;
+  col_map_block(m, blockIdx.x, z, slot);
+  if (z >= g.nz) return;   // idle block (uniform over the block)
   const unsigned mask = (1u << Q_G2) | (1u << Q_RHO2) | (1u << Q_GMAX) | (1u << Q_BAD);
-  block_reduce_write<256>(acc, mask, partial + ((int64_t)z * nbx + (int64_t)k * m.bt + ch) * NQ);
+  block_reduce_write<256>(acc, mask, partial + ((int64_t)z * nbx + slot) * NQ);
 }
 
 __global__ void __launch_bounds__(256) k_observe_finish(const double* __restrict__ partial, int nbx, Geom g,
@@ -247,7 +248,7 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
 
 // ---- pieces of the observing step (nt a multiple of 64: full column-map blocks) ----
 bool fused_observe_geometry(const Geom& g) { return g.nt % 64 == 0; }
-int fused_observe_blocks_per_layer(const Geom& g) { return NXCD * col_map(g, 256).bt; }
+int fused_observe_blocks_per_layer(const Geom& g) { return col_map_slots_per_layer(col_map(g, 256)); }
 template <typename G, typename T>
 void launch_obs_gauss(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c,
                       double* partial, hipStream_t st) {

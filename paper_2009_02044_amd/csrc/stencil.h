@@ -201,6 +201,9 @@ template <typename A> __device__ __forceinline__ A pull_alg(const A& v, int a) {
 // P(W^dag M W) = W^dag P(M) W.
 // The forward plaquettes at x, for the observables: projections and real traces of
 // U_{x,y}, U_{x,z}, U_{y,z}.
+#ifndef GL_PLAQ_ORDER
+#define GL_PLAQ_ORDER 1
+#endif
 template <typename G> struct PlaqObs {
   typename G::Alg p[3];
   typename G::Real tr[3];
@@ -237,7 +240,7 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
   for (int i = 0; i < 3; ++i) f[i] = G::alg_zero();
   const Site xpy = shifted(g, x, 1, +1), xpz = shifted(g, x, 2, +1);
   const Site xmy = shifted(g, x, 1, -1), xmz = shifted(g, x, 2, -1);
-  {
+  auto b_xy = [&]() {
     // plane (x, y): forward, and backward for y in -x
     L O0, O1, A, B;
     own(O0, 0);
@@ -264,8 +267,8 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
       acc(f[1], G::proj_mul(G::mul_dag(O1, G::mul(B2, A2)), C2), w0);
     }
     staple_fence();
-  }
-  {
+  };
+  auto b_xz = [&]() {
     // plane (x, z): forward, and backward for z in -x
     L O0, O2, A, B;
     own(O0, 0);
@@ -290,8 +293,8 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
       acc(f[2], G::proj_mul(G::mul_dag(O2, G::mul(B2, A2)), C2), w0);
     }
     staple_fence();
-  }
-  {
+  };
+  auto b_yz = [&]() {
     // plane (y, z): forward
     L O1, O2, A, B;
     own(O1, 1);
@@ -307,8 +310,8 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     acc(f[1], p, w2);
     acc(f[2], p, -w1);
     staple_fence();
-  }
-  {
+  };
+  auto b_my = [&]() {
     // backward in -y for x and z, sharing U_1(x-y)
     L Y1, O, A, B;
     fetch(Y1, 1, idx(g, xmy));                                // U_1(x-y)
@@ -322,8 +325,8 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     fetch(B, 2, idx(g, xmy));                                 // U_2(x-y)
     acc(f[2], G::proj_mul(G::mul_dag(O, G::mul(B, A)), Y1), w1);
     staple_fence();
-  }
-  {
+  };
+  auto b_mz = [&]() {
     // backward in -z for x and y, sharing U_2(x-z)
     L Z2, O, A, B;
     fetch(Z2, 2, idx(g, xmz));                                // U_2(x-z)
@@ -337,6 +340,22 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     fetch(B, 1, idx(g, xmz));                                 // U_1(x-z)
     acc(f[1], G::proj_mul(G::mul_dag(O, G::mul(B, A)), Z2), w2);
     staple_fence();
+  };
+  // Order of the plaquette groups (the force sums in this order).  The -z group first:
+  // its links of layer z - 1 are then loaded while the work-groups of that layer load
+  // them as their own, so they are still in the L2.
+  if constexpr (GL_PLAQ_ORDER == 1) {
+    b_mz();
+    b_xy();
+    b_xz();
+    b_yz();
+    b_my();
+  } else {
+    b_xy();
+    b_xz();
+    b_yz();
+    b_my();
+    b_mz();
   }
 }
 

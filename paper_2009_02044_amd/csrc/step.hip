@@ -182,11 +182,11 @@ __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __rest
     acc[Q_SL] = oa.sl;
     acc[Q_UNIT] = oa.uv;
     acc[Q_BAD] = (oa.bad || !isfinite(acc[Q_EPS])) ? 1.0 : 0.0;
-    const int k = (int)(blockIdx.x % NXCD);
-    const uint32_t j = blockIdx.x / NXCD;
-    const uint32_t col = (uint32_t)k * m.bt + j % (uint32_t)m.bt;
+    int zb;
+    uint32_t slot;
+    col_map_block(m, blockIdx.x, zb, slot);
     const unsigned mask = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_UNIT) | (1u << Q_BAD);
-    block_reduce_write<LF_BS, true>(acc, mask, partial + ((int64_t)x.z * NXCD * m.bt + col) * NQ);
+    block_reduce_write<LF_BS, true>(acc, mask, partial + ((int64_t)x.z * col_map_slots_per_layer(m) + slot) * NQ);
   }
 }
 
