@@ -20,6 +20,20 @@ Steps, in the paper's order:
    sum wherever the nuclei do not overlap.
    Periodic z uses a seam link U_z(x_T, Nz-1) = V_A(x_T, Nz-1) V_B^dag(x_T, 0) that
    makes the plaquettes across the boundary trivial.
+3'. Several sheets (longitudinal colour structure; Sec. 3 notes that charge densities
+   rho(x^+-, x_T) more general than eq. single_sheet are allowed, and Sec. 5 names the
+   stack of uncorrelated colour sheets).  The MV functional of Sec. 2 makes charges at
+   different x^+- independent, so the nucleus is cut into ns pieces of equal weight of
+   the profile, piece k carrying its own transverse charges rho_k (drawn with mu^2 / ns
+   each, so that the total charge has the single-sheet variance).  Piece k is crossed
+   while ns Lambda runs through [k, k + 1], with cumulative weight
+       lambda_k(z, t) = clip(ns Lambda(z, t) - k, 0, 1),
+   and within it the colour structure is that of rho_k, so the Wilson line is the
+   ordered product
+       V_N = exp(-i lambda_{ns-1} phi_{N,ns-1}) ... exp(-i lambda_1 phi_{N,1}) exp(-i lambda_0 phi_{N,0}),
+   the factor of the piece the path crosses later on the left (sheet 0 is the leading
+   edge: B's largest z, A's smallest z).  ns = 1 is step 3.  Identical sheets
+   (rho_k = rho / ns) commute and give the single sheet with rho.
 5. The links are built at t0 and t0 - dt; E(t0 - dt/2) = Log(U(t0) U^dag(t0 - dt)) /
    (i a_i dt) with the principal Log, so that eq. lattice_2 maps U(t0 - dt) onto U(t0).
 6. The CPIC particles (Sec. 3) carry the charge that the lattice Gauss law (eq. gauss)
@@ -29,7 +43,10 @@ Steps, in the paper's order:
 Pinned by tests/test_oracle_init.py: Poisson solve against the lattice Laplacian
 applied back, Lambda cut as a no-op below max |k~|, trivial seam and transverse
 plaquettes, exact reproduction of U(t0 - dt), Gauss law at t0, and a single nucleus
-carrying the light-like field of Sec. 2 (p_T ~ 0, p_L ~ eps).
+carrying the light-like field of Sec. 2 (p_T ~ 0, p_L ~ eps).  Sheets: identical sheets
+reduce to one sheet, the Wilson line behind a nucleus equals the ordered product of
+matrix exponentials of the sheets' fields (scipy's expm), Gauss law and trivial
+transverse plaquettes at t0, and a single multi-sheet nucleus stays light-like.
 """
 from dataclasses import dataclass
 import numpy as np
@@ -81,13 +98,25 @@ def profile_A(z, tau, mv):
     return 0.5 * erfc(-(z - mv.zA + tau) / (np.sqrt(2.0) * mv.sigma))
 
 
-def wilson_lines(phi_mat, prof):
-    """V(z, x_T) = exp(-i Lambda(z) phi(x_T)); phi_mat (ny, nx, N, N), prof (nz,)."""
-    return su.expi(-prof[:, None, None, None, None] * phi_mat[None])
+def sheet_weights(prof, ns):
+    """lambda_k(z) = clip(ns Lambda(z) - k, 0, 1) for k = 0..ns-1, shape (ns, nz)."""
+    k = np.arange(ns)[:, None]
+    return np.clip(ns * prof[None, :] - k, 0.0, 1.0)
+
+
+def wilson_lines(phi_mats, prof):
+    """V(z, x_T) = prod_k exp(-i lambda_k(z) phi_k(x_T)), later sheets to the left.
+    phi_mats (ns, ny, nx, N, N), prof (nz,)."""
+    lam = sheet_weights(prof, phi_mats.shape[0])
+    V = su.expi(-lam[0][:, None, None, None, None] * phi_mats[0][None])
+    for k in range(1, phi_mats.shape[0]):
+        V = su.expi(-lam[k][:, None, None, None, None] * phi_mats[k][None]) @ V
+    return V
 
 
 def links_at(phiA, phiB, nz, tau, p, mv):
-    """Links U (3, nz, ny, nx, N, N) of the superposed nuclei at t0 + tau."""
+    """Links U (3, nz, ny, nx, N, N) of the superposed nuclei at t0 + tau; phiA, phiB
+    (ns, ny, nx, N, N)."""
     z = np.arange(nz) * p.a_L
     VA = wilson_lines(phiA, profile_A(z, tau, mv))
     VB = wilson_lines(phiB, profile_B(z, tau, mv))
@@ -101,11 +130,21 @@ def links_at(phiA, phiB, nz, tau, p, mv):
     return U
 
 
+def sheet_fields(rhoT, p, mv):
+    """phi of every sheet as matrices (ns, ny, nx, N, N); rhoT (ng, nt, nt) for one
+    sheet or (ns, ng, nt, nt)."""
+    r = np.asarray(rhoT, dtype=np.float64)
+    if r.ndim == 3:
+        r = r[None]
+    return np.stack([su.from_components(np.moveaxis(poisson(rk, p.a_T, mv.m_ir, mv.uv_cut), 0, -1), p.nc)
+                     for rk in r])
+
+
 def initial_state(rhoT_A, rhoT_B, nz, p, mv):
-    """State at step 0 from the transverse charges (components, shape (ng, nt, nt))."""
-    nc = p.nc
-    phiA = su.from_components(np.moveaxis(poisson(rhoT_A, p.a_T, mv.m_ir, mv.uv_cut), 0, -1), nc)
-    phiB = su.from_components(np.moveaxis(poisson(rhoT_B, p.a_T, mv.m_ir, mv.uv_cut), 0, -1), nc)
+    """State at step 0 from the transverse charges: components of shape (ng, nt, nt)
+    (one sheet) or (ns, ng, nt, nt) (ns sheets, sheet 0 the leading edge)."""
+    phiA = sheet_fields(rhoT_A, p, mv)
+    phiB = sheet_fields(rhoT_B, p, mv)
     U0 = links_at(phiA, phiB, nz, 0.0, p, mv)
     U1 = links_at(phiA, phiB, nz, -p.dt, p, mv)
     a = p.a

@@ -29,6 +29,17 @@ def mv_charges(seed, nc, nt, mu, a_T):
     return A, B
 
 
+def mv_sheet_charges(seed, nc, nt, mu, a_T, ns):
+    """(rhoT_A, rhoT_B), each (ns, nc^2-1, nt, nt) float64: ns independent sheets per
+    nucleus, each with variance mu^2 / ns, so that their sum has the MV variance mu^2."""
+    g = rng(seed)
+    ng = nc * nc - 1
+    sd = mu / (a_T * np.sqrt(ns))
+    A = g.standard_normal((ns, ng, nt, nt)) * sd
+    B = g.standard_normal((ns, ng, nt, nt)) * sd
+    return A, B
+
+
 def normal(seed, shape, scale=1.0):
     return rng(seed).standard_normal(shape) * scale
 
@@ -67,7 +78,7 @@ class Workload:
         return self.nz * self.nt * self.nt
 
 
-# The five workloads of the method's evaluation (see the design doc for the recipe).
+# The workloads of the method's evaluation.
 SMALL_SU2 = Workload("su2-64x8x8", nc=2, nz=64, nt=8, mu=1.0, sigma=4.0, steps=100, seed=1001)
 PLAIN_SU3 = Workload("su3-512x64x64", nc=3, nz=512, nt=64, mu=0.5, sigma=8.0,
                      uv_cut=2.5, steps=1024, seed=2001)
