@@ -15,7 +15,8 @@ tiling, event-averaged T^{mu nu}(z)), the semi-implicit scheme on the headline
 lattice, the differentiation form (gradient of the central-slab energy after 256 steps of
 a 256 x 32 x 32 lattice, FP32 forward with checkpoints every 32 steps, FP64 reverse pass),
 the local rest frame at the collision point after the collision (eps_loc from diagonalising
-T^{mu nu}), optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
+T^{mu nu}), nuclei of 8 colour sheets along the beam axis against the single sheet (GPU
+initial conditions, energy between the receding nuclei), optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
 the FP64 CPU oracle timed on the host.
 """
 import argparse
@@ -145,6 +146,51 @@ def run_rest_frame(w, after=224, every=32):
         rows.append({"step": s_c + (k + 1) * every, "tau": tau, "eps_loc": el, "v": v,
                      "eps_loc_tau": el * tau, "2pT_over_eps_loc": 2 * pT / el, "pL_over_eps_loc": pL / el})
     return {"workload": w.name, "z_c": z_c, "t_c": t_c, "rows": rows}
+
+
+def run_sheets(w, ns=8, after=128, every=64):
+    """Nuclei with colour structure along the beam axis (ns independent sheets per
+    nucleus, mu^2 / ns each) against the single sheet of the same width and a single
+    sheet ns times thinner, on the headline lattice: time of the GPU initial conditions,
+    H at t0, then, after the collision, eps at the collision point, the energy between
+    the receding nuclei (|z - z_c| < t - t_c - 3 sigma) and H."""
+    import torch
+    import synth
+    import paper_2009_02044_amd as pkg
+    z_c, t_c = 0.5 * (w.zA + w.zB), 0.5 * (w.zA - w.zB)
+    kz = int(round(z_c / w.a_L))
+    s_c = int(round(t_c / w.dt))
+    z = np.arange(w.nz) * w.a_L
+    out = {"workload": w.name, "ns": ns, "z_c": z_c, "t_c": t_c}
+    for key, n, sig in (("ns1", 1, w.sigma), ("ns%d" % ns, ns, w.sigma), ("ns1_thin", 1, w.sigma / ns)):
+        lat = pkg.Lattice(nc=w.nc, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=w.dt, fp=64)
+        if n == 1:
+            rA, rB = synth.mv_charges(w.seed, w.nc, w.nt, w.mu, w.a_T)
+        else:
+            rA, rB = synth.mv_sheet_charges(w.seed, w.nc, w.nt, w.mu, w.a_T, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=sig, zA=w.zA, zB=w.zB)
+        torch.cuda.synchronize()
+        init_ms = (time.perf_counter() - t0) * 1e3
+        H0 = lat.observables()["energy"]
+        obs = lat.obs_buffer()
+        lat.step(s_c)
+        rows = []
+        for k in range(after // every):
+            lat.step(every)
+            lat.observe(obs)
+            torch.cuda.synchronize()
+            o = pkg.Lattice.unpack_obs(obs, w.nz)
+            eps = o["tmunu_z"][0]
+            tau = (s_c + (k + 1) * every) * w.dt - t_c
+            inner = np.abs(z - z_c) < tau - 3 * w.sigma
+            rows.append({"tau": tau, "eps_zc": float(eps[kz]),
+                         "glasma_energy": float(eps[inner].sum() * w.a_L * w.a_T ** 2 * w.nt ** 2),
+                         "H": float(o["energy"]), "gauss_rel": float(o["gauss_rel"])})
+        out[key] = {"sheets": n, "sigma": sig, "init_ms": init_ms, "H0": H0, "rows": rows}
+        del lat
+    return out
 
 
 def run_batched(steps, warmup, graph_chunk=16):
@@ -300,6 +346,7 @@ def main():
     ap.add_argument("--semi-steps", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rest-frame", action="store_true")
+    ap.add_argument("--no-sheets", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
     ap.add_argument("--precision-steps", type=int, default=2048)
@@ -362,6 +409,13 @@ def main():
         print(f"[bench] rest frame at z_c: tau {r['tau']:.0f}, eps_loc tau {r['eps_loc_tau']:.3e}, "
               f"2pT/eps_loc {r['2pT_over_eps_loc']:.3f}, pL/eps_loc {r['pL_over_eps_loc']:.3f}",
               file=sys.stderr, flush=True)
+    if not args.no_sheets:
+        forms["colour_sheets"] = r = run_sheets(w)
+        one, many, thin = r["ns1"], r["ns%d" % r["ns"]], r["ns1_thin"]
+        a, b, c = one["rows"][-1], many["rows"][-1], thin["rows"][-1]
+        print(f"[bench] {r['ns']} colour sheets: init {many['init_ms']:.1f} ms (1 sheet {one['init_ms']:.1f} ms); "
+              f"at tau {a['tau']:.0f} glasma energy {b['glasma_energy']:.4g} vs {a['glasma_energy']:.4g} (1 sheet) "
+              f"and {c['glasma_energy']:.4g} (1 sheet, sigma/{r['ns']})", file=sys.stderr, flush=True)
     if args.precision_study:
         wp = synth.PRECISION_SU3
         forms["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)

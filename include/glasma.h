@@ -131,6 +131,24 @@ int glasma_init_state(glasma_ctx* ctx, const double* U, const double* E, const d
  * MV ensemble is an input).  Sets step = 0.  Asynchronous after the upload. */
 int glasma_init_mv(glasma_ctx* ctx, const glasma_mv* mv, const double* rhoT_A, const double* rhoT_B);
 
+/* Nuclei whose colour structure varies along the beam axis (Sec. 3 allows charge
+ * densities rho(x^+-, x_T) beyond eq. single_sheet; Sec. 5 names the stack of
+ * uncorrelated sheets): each nucleus is cut into ns pieces of equal weight of its
+ * Gaussian profile, piece k carrying the transverse charges of sheet k, and the
+ * Wilson line of Sec. 2 is the path-ordered product
+ *   V = exp(-i lambda_0 phi_0) ... exp(-i lambda_{ns-1} phi_{ns-1}),
+ *   lambda_k = clamp(ns Lambda - k, 0, 1)   (Lambda: the profile's cumulative weight),
+ * sheet 0 the leading edge (largest z for B, smallest for A), each later sheet to the
+ * right (so that, with A_i = V d_i V^dag / (ig), the field inside piece k is sheet k's
+ * own rotated by the completed pieces).  rhoT_A, rhoT_B: host
+ * double, [ns][n_g][nt][nt] (for the MV ensemble of one sheet with variance mu^2, draw
+ * each sheet with mu^2 / ns).  ns = 1 is glasma_init_mv.  For ns > 1 the sheets' fields
+ * are staged in the second link buffer: ns * 2 * n_g * nt^2 doubles must fit there
+ * (ns <= nz always does), else GLASMA_E_ARG.  Sets step = 0.  Asynchronous after the
+ * uploads (the host arrays may be released on return). */
+int glasma_init_mv_sheets(glasma_ctx* ctx, const glasma_mv* mv, int32_t ns, const double* rhoT_A,
+                          const double* rhoT_B);
+
 /* Advance n >= 0 steps (leapfrog or semi-implicit per params, CPIC hops on the steps
  * the schedule S(s) = floor((s + 1/2) dt/a_L + 1/2) advances, reunitarisation every
  * reunit_every steps when set).  Asynchronous for the leapfrog. */

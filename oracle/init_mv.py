@@ -30,9 +30,14 @@ Steps, in the paper's order:
        lambda_k(z, t) = clip(ns Lambda(z, t) - k, 0, 1),
    and within it the colour structure is that of rho_k, so the Wilson line is the
    ordered product
-       V_N = exp(-i lambda_{ns-1} phi_{N,ns-1}) ... exp(-i lambda_1 phi_{N,1}) exp(-i lambda_0 phi_{N,0}),
-   the factor of the piece the path crosses later on the left (sheet 0 is the leading
-   edge: B's largest z, A's smallest z).  ns = 1 is step 3.  Identical sheets
+       V_N = exp(-i lambda_0 phi_{N,0}) exp(-i lambda_1 phi_{N,1}) ... exp(-i lambda_{ns-1} phi_{N,ns-1}),
+   the factor of the piece the path crosses later on the right (sheet 0 is the leading
+   edge: B's largest z, A's smallest z).  The order follows from the form
+   A_i = V d_i V^dag / (ig) of eq. 3d_colorfield_1: inside piece k, V = W e_k with W the
+   completed pieces, so d_z A_i = W d_z(e_k d_i e_k^dag) W^dag and the field strength there
+   is that of sheet k alone, rotated by W, as gauge covariance of the covariant-gauge
+   field d_i phi_k demands (with e_k on the left it would pick up commutators of phi_k
+   with the earlier sheets' pure gauge).  ns = 1 is step 3.  Identical sheets
    (rho_k = rho / ns) commute and give the single sheet with rho.
 5. The links are built at t0 and t0 - dt; E(t0 - dt/2) = Log(U(t0) U^dag(t0 - dt)) /
    (i a_i dt) with the principal Log, so that eq. lattice_2 maps U(t0 - dt) onto U(t0).
@@ -45,8 +50,10 @@ applied back, Lambda cut as a no-op below max |k~|, trivial seam and transverse
 plaquettes, exact reproduction of U(t0 - dt), Gauss law at t0, and a single nucleus
 carrying the light-like field of Sec. 2 (p_T ~ 0, p_L ~ eps).  Sheets: identical sheets
 reduce to one sheet, the Wilson line behind a nucleus equals the ordered product of
-matrix exponentials of the sheets' fields (scipy's expm), Gauss law and trivial
-transverse plaquettes at t0, and a single multi-sheet nucleus stays light-like.
+matrix exponentials of the sheets' fields (scipy's expm), the field energy of a
+multi-sheet nucleus is the sum of those of its sheets taken alone (gauge covariance),
+Gauss law and trivial transverse plaquettes at t0, and a single multi-sheet nucleus
+stays light-like.
 """
 from dataclasses import dataclass
 import numpy as np
@@ -105,12 +112,12 @@ def sheet_weights(prof, ns):
 
 
 def wilson_lines(phi_mats, prof):
-    """V(z, x_T) = prod_k exp(-i lambda_k(z) phi_k(x_T)), later sheets to the left.
+    """V(z, x_T) = prod_k exp(-i lambda_k(z) phi_k(x_T)), later sheets to the right.
     phi_mats (ns, ny, nx, N, N), prof (nz,)."""
     lam = sheet_weights(prof, phi_mats.shape[0])
     V = su.expi(-lam[0][:, None, None, None, None] * phi_mats[0][None])
     for k in range(1, phi_mats.shape[0]):
-        V = su.expi(-lam[k][:, None, None, None, None] * phi_mats[k][None]) @ V
+        V = V @ su.expi(-lam[k][:, None, None, None, None] * phi_mats[k][None])
     return V
 
 

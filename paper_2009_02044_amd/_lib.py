@@ -55,6 +55,7 @@ def _load():
         "glasma_destroy": ([P], C.c_int),
         "glasma_init_state": ([P, D, D, D, D, I64], C.c_int),
         "glasma_init_mv": ([P, C.POINTER(MV), D, D], C.c_int),
+        "glasma_init_mv_sheets": ([P, C.POINTER(MV), I32, D, D], C.c_int),
         "glasma_step": ([P, I32], C.c_int),
         "glasma_deposit_current": ([P, V], C.c_int),
         "glasma_observe": ([P, V], C.c_int),

@@ -260,23 +260,33 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
   return GLASMA_OK;
 }
 
-int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, const double* rhoT_B) {
+int glasma_init_mv_sheets(glasma_ctx* c, const glasma_mv* mv, int32_t ns, const double* rhoT_A,
+                          const double* rhoT_B) {
   if (!c || !mv || !rhoT_A || !rhoT_B) return fail(c, GLASMA_E_ARG, "NULL argument");
   if (!(mv->m_ir > 0) || !(mv->sigma > 0)) return fail(c, GLASMA_E_ARG, "m_ir and sigma must be > 0");
+  if (ns < 1) return fail(c, GLASMA_E_ARG, "ns must be >= 1");
   const size_t m = (size_t)c->ng * c->g.layer;
+  // the fields of several sheets are held in the second link buffer, free until the first step
+  const size_t ubytes = 3 * (size_t)c->rs * c->g.Vp * (c->p.fp == 64 ? 8 : 4);
+  if (ns > 1 && (size_t)ns * 2 * m * sizeof(double) > ubytes)
+    return fail(c, GLASMA_E_ARG, "too many sheets for this lattice (ns * 2 * n_g * nt^2 doubles must fit the "
+                                 "second link buffer)");
   double* work = (double*)c->b.work;
-  HIPCHK(c, hipMemcpyAsync(work, rhoT_A, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(work + m, rhoT_B, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double* phi = ns == 1 ? work + 2 * m : (double*)c->b.U_alt;
   McvConst k{mv->m_ir, mv->uv_cut, mv->sigma, mv->zA, mv->zB};
   c->adj_ok = false;
   c->step = 0;
   c->cur = 0;
   c->offA = c->offB = 0;
   StepConst sc = step_const(c);
+  for (int32_t q = 0; q < ns; ++q) {
+    HIPCHK(c, hipMemcpyAsync(work, rhoT_A + q * m, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(work + m, rhoT_B + q * m, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    launch_ic_phi(work, phi + (size_t)q * 2 * m, c->ng, c->g, sc, k, c->stream);
+  }
   dispatch(c, [&]<typename G, typename T>() -> int {
-    launch_init_mv<G, T>(work, work, (T*)c->b.U, (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, k,
-                         c->stream);
+    launch_ic_fields<G, T>(phi, ns, (T*)c->b.U, (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, k, c->stream);
     if (c->p.scheme == 1) {
       // charges that make the conserved combination D.(E + dt f1(U(t0), U(t0 - dt))) - rho vanish
       const SemiRegion r = semi_region(&c->p);
@@ -292,6 +302,10 @@ int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, con
   HIPCHK(c, hipGetLastError());
   c->ready = true;
   return GLASMA_OK;
+}
+
+int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, const double* rhoT_B) {
+  return glasma_init_mv_sheets(c, mv, 1, rhoT_A, rhoT_B);
 }
 
 // One semi-implicit step: U(t - dt), f1(U(t), U(t - dt)) and the hop once, then fixed-point

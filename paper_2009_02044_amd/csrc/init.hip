@@ -12,6 +12,14 @@
 //    cumulative normalised Gaussian profile is
 //      Lambda_B = erfc((z - z_B - (t - t0)) / (sqrt 2 sigma)) / 2   (B moves +z),
 //      Lambda_A = erfc(-(z - z_A + (t - t0)) / (sqrt 2 sigma)) / 2  (A moves -z).
+//    With ns sheets (colour structure varying along the beam axis, independent
+//    charges per piece of equal profile weight, Sec. 3 after eq. single_sheet and
+//    Sec. 5) the line is the path-ordered product
+//      V_N = exp(-i lambda_0 phi_{N,0}) ... exp(-i lambda_{ns-1} phi_{N,ns-1}),
+//      lambda_k = clamp(ns Lambda_N - k, 0, 1),
+//    the sheet crossed later on the right: with A_i = V d_i V^dag / (ig), the field
+//    strength inside piece k is then sheet k's own, rotated by the completed pieces
+//    (gauge covariance); sheets not reached yet (lambda_k = 0) are 1.
 // 3. U_i = [V_A(x) V_A^dag(x+i)] [V_B(x) V_B^dag(x+i)] (i = x, y), U_z = 1 except the
 //    periodic seam U_z(x_T, nz-1) = V_A(x_T, nz-1) V_B^dag(x_T, 0), at t0 and t0 - dt.
 // 4. E_i(t0 - dt/2) = -i Log(U_i(t0) U_i^dag(t0 - dt)) / (a_i dt), principal Log.
@@ -71,13 +79,24 @@ __global__ void k_dft(const double* __restrict__ in, double* __restrict__ out, i
 }
 
 template <typename Gd>
-__device__ __forceinline__ typename Gd::Link wilson(const double* __restrict__ phi, int nucleus, int64_t t,
-                                                    int64_t layer, double lam) {
+__device__ __forceinline__ typename Gd::Alg sheet_phi(const double* __restrict__ phi, int sheet, int nucleus,
+                                                      int64_t t, int64_t layer) {
   typename Gd::Alg p;
   constexpr int NG = Gd::NG;
 #pragma unroll
-  for (int k = 0; k < NG; ++k) p.c[k] = phi[((int64_t)nucleus * NG + k) * layer + t];
-  return Gd::expi(p, -lam);
+  for (int k = 0; k < NG; ++k) p.c[k] = phi[(((int64_t)sheet * 2 + nucleus) * NG + k) * layer + t];
+  return p;
+}
+// V_N at transverse site t for cumulative profile weight lam of the whole nucleus
+template <typename Gd>
+__device__ typename Gd::Link wilson(const double* __restrict__ phi, int ns, int nucleus, int64_t t, int64_t layer,
+                                    double lam) {
+  typename Gd::Link V = Gd::expi(sheet_phi<Gd>(phi, 0, nucleus, t, layer), -fmin(fmax(ns * lam, 0.0), 1.0));
+  for (int k = 1; k < ns; ++k) {
+    const double lk = fmin(fmax(ns * lam - k, 0.0), 1.0);
+    if (lk > 0.0) V = Gd::mul(V, Gd::expi(sheet_phi<Gd>(phi, k, nucleus, t, layer), -lk));
+  }
+  return V;
 }
 
 __device__ __forceinline__ double profileA(double z, double tau, const McvConst& mv) {
@@ -88,14 +107,14 @@ __device__ __forceinline__ double profileB(double z, double tau, const McvConst&
 }
 
 template <typename Gd>
-__device__ typename Gd::Link ic_link(const double* __restrict__ phi, const Geom& g, int x, int y, int z, int i,
-                                     double tau, double a_L, const McvConst& mv) {
+__device__ typename Gd::Link ic_link(const double* __restrict__ phi, int ns, const Geom& g, int x, int y, int z,
+                                     int i, double tau, double a_L, const McvConst& mv) {
   using L = typename Gd::Link;
   const int64_t t = (int64_t)y * g.nt + x;
   if (i == 2) {
     if (z != g.nz - 1) return Gd::one();
-    L VA = wilson<Gd>(phi, 0, t, g.layer, profileA((g.nz - 1) * a_L, tau, mv));
-    L VB = wilson<Gd>(phi, 1, t, g.layer, profileB(0.0, tau, mv));
+    L VA = wilson<Gd>(phi, ns, 0, t, g.layer, profileA((g.nz - 1) * a_L, tau, mv));
+    L VB = wilson<Gd>(phi, ns, 1, t, g.layer, profileB(0.0, tau, mv));
     return Gd::mul_dag(VA, VB);
   }
   const int xp = i == 0 ? wrap_add(x, 1, g.nt) : x;
@@ -103,21 +122,21 @@ __device__ typename Gd::Link ic_link(const double* __restrict__ phi, const Geom&
   const int64_t tp = (int64_t)yp * g.nt + xp;
   const double zz = z * a_L;
   const double lA = profileA(zz, tau, mv), lB = profileB(zz, tau, mv);
-  L UA = Gd::mul_dag(wilson<Gd>(phi, 0, t, g.layer, lA), wilson<Gd>(phi, 0, tp, g.layer, lA));
-  L UB = Gd::mul_dag(wilson<Gd>(phi, 1, t, g.layer, lB), wilson<Gd>(phi, 1, tp, g.layer, lB));
+  L UA = Gd::mul_dag(wilson<Gd>(phi, ns, 0, t, g.layer, lA), wilson<Gd>(phi, ns, 0, tp, g.layer, lA));
+  L UB = Gd::mul_dag(wilson<Gd>(phi, ns, 1, t, g.layer, lB), wilson<Gd>(phi, ns, 1, tp, g.layer, lB));
   return Gd::mul(UA, UB);
 }
 
 template <typename Gd, typename T>
-__global__ void k_ic_links(const double* __restrict__ phi, T* __restrict__ U, T* __restrict__ E, Geom g,
+__global__ void k_ic_links(const double* __restrict__ phi, int ns, T* __restrict__ U, T* __restrict__ E, Geom g,
                            StepConst c, McvConst mv) {
   constexpr int NG = Gd::NG;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int x = (int)(s % g.nt), y = (int)((s / g.nt) % g.nt), z = (int)(s / g.layer);
   for (int i = 0; i < 3; ++i) {
-    typename Gd::Link U0 = ic_link<Gd>(phi, g, x, y, z, i, 0.0, c.a[2], mv);
-    typename Gd::Link U1 = ic_link<Gd>(phi, g, x, y, z, i, -c.dt, c.a[2], mv);
+    typename Gd::Link U0 = ic_link<Gd>(phi, ns, g, x, y, z, i, 0.0, c.a[2], mv);
+    typename Gd::Link U1 = ic_link<Gd>(phi, ns, g, x, y, z, i, -c.dt, c.a[2], mv);
     typename Gd::Alg e = Gd::logi(Gd::mul_dag(U0, U1));
     const double k = 1.0 / (c.a[i] * c.dt);
     for (int q = 0; q < NG; ++q) e.c[q] *= k;
@@ -158,23 +177,27 @@ __global__ void k_ic_gauss(const T* __restrict__ U, const T* __restrict__ E, con
   store_alg(isB ? zero : r, rhoA, 0, s, Vp);
 }
 
-template <typename G, typename T>
-void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T* rhoB, const Geom& g,
-                    const StepConst& c, const McvConst& mv, hipStream_t st) {
-  using Gd = typename GroupOf<G::NC, double>::type;
-  const int nb = 2 * G::NG;
+void launch_ic_phi(double* work, double* phi_out, int ng, const Geom& g, const StepConst& c, const McvConst& mv,
+                   hipStream_t st) {
+  const int nb = 2 * ng;
   const int64_t m = (int64_t)nb * g.layer;
-  double* phi = work + m;
   double* c1 = work + 2 * m;
   double* c2 = work + 4 * m;
   const int bs = 256;
   const unsigned gb = (unsigned)((m + bs - 1) / bs);
-  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, rhoT_dev, c1, g.nt, nb, 0, c.a[0], mv.m_ir, mv.uv_cut);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, work, c1, g.nt, nb, 0, c.a[0], mv.m_ir, mv.uv_cut);
   hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, c2, g.nt, nb, 1, c.a[0], mv.m_ir, mv.uv_cut);
   hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c2, c1, g.nt, nb, 2, c.a[0], mv.m_ir, mv.uv_cut);
-  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, phi, g.nt, nb, 3, c.a[0], mv.m_ir, mv.uv_cut);
+  hipLaunchKernelGGL(k_dft, dim3(gb), dim3(bs), 0, st, c1, phi_out, g.nt, nb, 3, c.a[0], mv.m_ir, mv.uv_cut);
+}
+
+template <typename G, typename T>
+void launch_ic_fields(const double* phi, int ns, T* U, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
+                      const McvConst& mv, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int bs = 256;
   const unsigned sb = (unsigned)((g.V + bs - 1) / bs);
-  hipLaunchKernelGGL((k_ic_links<Gd, T>), dim3(sb), dim3(bs), 0, st, phi, U, E, g, c, mv);
+  hipLaunchKernelGGL((k_ic_links<Gd, T>), dim3(sb), dim3(bs), 0, st, phi, ns, U, E, g, c, mv);
   // the semi-implicit scheme conserves D.(E + dt f1(U(t0), U(t0 - dt))) - rho instead;
   // its caller builds f1 and sets the charges through launch_gauss_charges
   if (c.scheme == 1) return;
@@ -196,9 +219,12 @@ GL_GC_INST(Su2<double>, double)
 GL_GC_INST(Su3<double>, double)
 GL_GC_INST(Su2<float>, float)
 GL_GC_INST(Su3<float>, float)
-template void launch_init_mv<Su2<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
-template void launch_init_mv<Su3<double>, double>(const double*, double*, double*, double*, double*, double*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
-template void launch_init_mv<Su2<float>, float>(const double*, double*, float*, float*, float*, float*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
-template void launch_init_mv<Su3<float>, float>(const double*, double*, float*, float*, float*, float*, const Geom&, const StepConst&, const McvConst&, hipStream_t);
+#define GL_IC_INST(G, T) \
+  template void launch_ic_fields<G, T>(const double*, int, T*, T*, T*, T*, const Geom&, const StepConst&, \
+                                       const McvConst&, hipStream_t);
+GL_IC_INST(Su2<double>, double)
+GL_IC_INST(Su3<double>, double)
+GL_IC_INST(Su2<float>, float)
+GL_IC_INST(Su3<float>, float)
 
 }  // namespace gl

@@ -82,15 +82,20 @@ void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, cons
 template <typename G, typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 
-// Initial conditions: rhoT_dev holds the transverse charges of both nuclei
-// (double, [2][NG][nt*nt]: A then B); work needs ic_work_doubles(g, NG) doubles.
+// Initial conditions.  launch_ic_phi: the transverse charges of one sheet of both
+// nuclei (double, [2][NG][nt*nt]: A then B, at the start of work; work needs
+// ic_work_doubles(g, NG) doubles) -> their fields phi, written to phi_out in the same
+// layout.  launch_ic_fields: links, E and charges from the fields of ns sheets
+// (phi: [ns][2][NG][nt*nt], sheet 0 the leading edge of each nucleus).
 struct McvConst {
   double m_ir, uv_cut, sigma, zA, zB;
 };
 size_t ic_work_doubles(const Geom& g, int ng);
+void launch_ic_phi(double* work, double* phi_out, int ng, const Geom& g, const StepConst& c, const McvConst& mv,
+                   hipStream_t st);
 template <typename G, typename T>
-void launch_init_mv(const double* rhoT_dev, double* work, T* U, T* E, T* rhoA, T* rhoB,
-                    const Geom& g, const StepConst& c, const McvConst& mv, hipStream_t st);
+void launch_ic_fields(const double* phi, int ns, T* U, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
+                      const McvConst& mv, hipStream_t st);
 // charges from the (modified) Gauss law: rho = D.(E + scale F2), F2 may be null; split at nz/2
 template <typename G, typename T>
 void launch_gauss_charges(const T* U, const T* E, const T* F2, double scale, T* rhoA, T* rhoB, const Geom& g,

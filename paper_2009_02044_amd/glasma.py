@@ -69,12 +69,19 @@ class Lattice:
         self._chk(lib.glasma_init_state(self.ctx, *[dptr(a) for a in arrs], int(step0)))
 
     def init_mv(self, rhoT_A, rhoT_B, m_ir=0.2, uv_cut=0.0, sigma=4.0, zA=None, zB=None):
+        """MV nuclei from transverse charges (n_g, nt, nt) per nucleus, or (ns, n_g, nt, nt)
+        for ns colour sheets along the beam axis (glasma_init_mv_sheets)."""
         zA = 0.75 * self.nz * self.params.a_L if zA is None else zA
         zB = 0.25 * self.nz * self.params.a_L if zB is None else zB
         mv = _lib.MV(m_ir, uv_cut, sigma, zA, zB)
         a = np.ascontiguousarray(rhoT_A, dtype=np.float64)
         b = np.ascontiguousarray(rhoT_B, dtype=np.float64)
-        self._chk(lib.glasma_init_mv(self.ctx, C.byref(mv), dptr(a), dptr(b)))
+        if a.shape != b.shape or a.ndim not in (3, 4):
+            raise ValueError("rhoT_A and rhoT_B must both be (n_g, nt, nt) or (ns, n_g, nt, nt)")
+        if a.ndim == 3:
+            self._chk(lib.glasma_init_mv(self.ctx, C.byref(mv), dptr(a), dptr(b)))
+        else:
+            self._chk(lib.glasma_init_mv_sheets(self.ctx, C.byref(mv), int(a.shape[0]), dptr(a), dptr(b)))
 
     def step(self, n=1):
         self._chk(lib.glasma_step(self.ctx, int(n)))
