@@ -16,7 +16,8 @@ lattice, the differentiation form (gradient of the central-slab energy after 256
 a 256 x 32 x 32 lattice, FP32 forward with checkpoints every 32 steps, FP64 reverse pass),
 the local rest frame at the collision point after the collision (eps_loc from diagonalising
 T^{mu nu}), nuclei of 8 colour sheets along the beam axis against the single sheet (GPU
-initial conditions, energy between the receding nuclei), optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
+initial conditions, energy between the receding nuclei), the approach of thin nuclei to the
+boost-invariant Glasma at mid-rapidity, optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
 the FP64 CPU oracle timed on the host.
 """
 import argparse
@@ -193,6 +194,43 @@ def run_sheets(w, ns=8, after=128, every=64):
     return out
 
 
+def run_bi_limit(sigmas=(8.0, 4.0, 2.0, 1.0)):
+    """Boost-invariant limit at mid-rapidity (Sec. 2, eqs. glasma_ic1/2): a lattice fine
+    along z (a_T = 16 a_L, 96 x 32 x 32, dilute MV charges), nuclei of width sigma; after
+    the collision, p_T(z_c) against eps_0 of the tau = 0+ boost-invariant fields of the
+    same nuclei (glasma_bi_fields) and p_L / eps at z_c, for the leapfrog (dt = a_L/2)
+    and the semi-implicit scheme (dt = a_L)."""
+    import synth
+    import paper_2009_02044_amd as pkg
+    nc, nt, nz, aT = 3, 32, 96, 16.0
+    m, mu, zA, zB = 0.8 / aT, 1.4 / aT, 72.0, 24.0
+    rA, rB = synth.mv_charges(77, nc, nt, mu, aT)
+    t_c, z_c = 0.5 * (zA - zB), int(0.5 * (zA + zB))
+    out = {"lattice": [nz, nt, nt], "a_T": aT, "mu": mu, "m": m, "rows": []}
+    for scheme, dt in ((0, 0.5), (1, 1.0)):
+        for sig in sigmas:
+            e0 = pkg.boost_invariant_fields(nc, nt, rA, rB, a_T=aT, m_ir=m)["eps0"]
+            lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=aT, a_L=1.0, dt=dt, fp=64, scheme=scheme,
+                              max_iter=300, tol=1e-12)
+            lat.init_mv(rA, rB, m_ir=m, uv_cut=0.0, sigma=sig, zA=zA, zB=zB)
+            s_c = int(round(t_c / dt))
+            per = int(round(2 / dt))
+            lat.step(s_c)
+            taus, pt, pl = [], [], []
+            for k in range(10):
+                lat.step(per)
+                sl = lat.observables()["tmunu_z"]
+                taus.append(2.0 * (k + 1))
+                pt.append(float(sl[2][z_c] / e0))
+                pl.append(float(sl[1][z_c] / sl[0][z_c]))
+            i, j = int(np.argmax(pt)), int(np.argmin(pl))
+            out["rows"].append({"scheme": "semi-implicit" if scheme else "leapfrog", "dt": dt, "sigma": sig,
+                                "eps0": e0, "pT_over_eps0_max": pt[i], "tau_at_max": taus[i],
+                                "pL_over_eps_min": pl[j], "tau_at_min": taus[j]})
+            del lat
+    return out
+
+
 def run_batched(steps, warmup, graph_chunk=16):
     """64 events, SU(3) FP32: autotuned tiling, then the timed run; returns throughput and
     the event-averaged T^{mu nu}(z) per N_z class (transverse means averaged over events)."""
@@ -347,6 +385,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rest-frame", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
+    ap.add_argument("--no-bi-limit", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
     ap.add_argument("--precision-steps", type=int, default=2048)
@@ -416,6 +455,13 @@ def main():
         print(f"[bench] {r['ns']} colour sheets: init {many['init_ms']:.1f} ms (1 sheet {one['init_ms']:.1f} ms); "
               f"at tau {a['tau']:.0f} glasma energy {b['glasma_energy']:.4g} vs {a['glasma_energy']:.4g} (1 sheet) "
               f"and {c['glasma_energy']:.4g} (1 sheet, sigma/{r['ns']})", file=sys.stderr, flush=True)
+    if not args.no_bi_limit:
+        forms["boost_invariant_limit"] = r = run_bi_limit()
+        for row in r["rows"]:
+            if row["scheme"] == "semi-implicit":
+                print(f"[bench] boost-invariant limit, semi-implicit, sigma {row['sigma']:g}: "
+                      f"max p_T/eps_0 {row['pT_over_eps0_max']:.3f}, min p_L/eps {row['pL_over_eps_min']:+.3f}",
+                      file=sys.stderr, flush=True)
     if args.precision_study:
         wp = synth.PRECISION_SU3
         forms["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)

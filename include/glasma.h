@@ -149,6 +149,27 @@ int glasma_init_mv(glasma_ctx* ctx, const glasma_mv* mv, const double* rhoT_A, c
 int glasma_init_mv_sheets(glasma_ctx* ctx, const glasma_mv* mv, int32_t ns, const double* rhoT_A,
                           const double* rhoT_B);
 
+/* Boost-invariant Glasma at tau = 0+ (Sec. 2, eqs. glasma_ic1, glasma_ic2, LC_gauge1): the
+ * longitudinal fields that infinitely thin nuclei with these transverse charges leave at
+ * the boundary of the forward light cone, the reference that thin nuclei approach at
+ * mid-rapidity.  With alpha^i_N = P(V_N(x) V_N^dag(x + i)) / a_T on the transverse links
+ * (V_N the Wilson line behind nucleus N: exp(-i phi_N), or the ordered product over ns
+ * sheets as in glasma_init_mv_sheets; P the hermitian traceless part of
+ * (W - W^dag)/(2i)) and g = 1:
+ *   E_z = -i [alpha_A^i, alpha_B^i]  (at the sites, each commutator averaged over the two
+ *          links of direction i that meet there),
+ *   B_z = -i ([alpha_A^x, alpha_B^y] - [alpha_A^y, alpha_B^x])  (at the xy plaquette
+ *          centres, alpha^x averaged over the plaquette's x links, alpha^y over its y links).
+ * p: nc, nt and a_T are used (the other fields must be valid); mv: m_ir, uv_cut (sigma,
+ * zA, zB unused).  rhoT_A, rhoT_B: host double, [ns][n_g][nt][nt].  work: device scratch
+ * of glasma_bi_work_bytes bytes.  Ez, Bz: device double [n_g][nt][nt] (component-major,
+ * Bz(x) belongs to the plaquette at x, x + e_x, x + e_x + e_y, x + e_y); out3: device
+ * double[3] = transverse means (eps_0, E_z^2/2, B_z^2/2), |X|^2 = sum_a X^a X^a.
+ * Asynchronous on `stream` (a hipStream_t; NULL = default) after the uploads. */
+int glasma_bi_work_bytes(const glasma_params* p, size_t* bytes);
+int glasma_bi_fields(const glasma_params* p, const glasma_mv* mv, int32_t ns, const double* rhoT_A,
+                     const double* rhoT_B, void* work, double* Ez, double* Bz, double* out3, void* stream);
+
 /* Advance n >= 0 steps (leapfrog or semi-implicit per params, CPIC hops on the steps
  * the schedule S(s) = floor((s + 1/2) dt/a_L + 1/2) advances, reunitarisation every
  * reunit_every steps when set).  Asynchronous for the leapfrog. */

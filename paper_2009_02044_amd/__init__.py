@@ -7,6 +7,7 @@ The compute path is libglasma.so only; importing this package fails if it is
 missing.  torch provides device memory and the stream.
 """
 from ._lib import lib, GlasmaError, LIB_PATH  # noqa: F401  (raises if the library is missing)
-from .glasma import Lattice, Batch, SlabEnergy, host_group_op  # noqa: F401
+from .glasma import Lattice, Batch, SlabEnergy, host_group_op, boost_invariant_fields  # noqa: F401
 
-__all__ = ["Lattice", "Batch", "SlabEnergy", "GlasmaError", "host_group_op", "lib", "LIB_PATH"]
+__all__ = ["Lattice", "Batch", "SlabEnergy", "GlasmaError", "host_group_op", "boost_invariant_fields", "lib",
+           "LIB_PATH"]

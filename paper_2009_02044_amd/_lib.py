@@ -56,6 +56,8 @@ def _load():
         "glasma_init_state": ([P, D, D, D, D, I64], C.c_int),
         "glasma_init_mv": ([P, C.POINTER(MV), D, D], C.c_int),
         "glasma_init_mv_sheets": ([P, C.POINTER(MV), I32, D, D], C.c_int),
+        "glasma_bi_work_bytes": ([C.POINTER(Params), C.POINTER(C.c_size_t)], C.c_int),
+        "glasma_bi_fields": ([C.POINTER(Params), C.POINTER(MV), I32, D, D, V, V, V, V, V], C.c_int),
         "glasma_step": ([P, I32], C.c_int),
         "glasma_deposit_current": ([P, V], C.c_int),
         "glasma_observe": ([P, V], C.c_int),

@@ -308,6 +308,51 @@ int glasma_init_mv(glasma_ctx* c, const glasma_mv* mv, const double* rhoT_A, con
   return glasma_init_mv_sheets(c, mv, 1, rhoT_A, rhoT_B);
 }
 
+// ---- boost-invariant tau = 0+ fields of two nuclei ------------------------------
+
+int glasma_bi_work_bytes(const glasma_params* p, size_t* bytes) {
+  int rc = check_params(p, nullptr, nullptr);
+  if (rc) return rc;
+  if (!bytes) return fail(nullptr, GLASMA_E_ARG, "bytes is NULL");
+  const Geom g = geom_of(p);
+  *bytes = bi_work_doubles(g, p->nc * p->nc - 1, p->nc == 3 ? 18 : 4) * sizeof(double);
+  return GLASMA_OK;
+}
+
+int glasma_bi_fields(const glasma_params* p, const glasma_mv* mv, int32_t ns, const double* rhoT_A,
+                     const double* rhoT_B, void* work, double* Ez, double* Bz, double* out3, void* stream) {
+  int rc = check_params(p, nullptr, nullptr);
+  if (rc) return rc;
+  if (!mv || !rhoT_A || !rhoT_B || !work || !Ez || !Bz || !out3) return fail(nullptr, GLASMA_E_ARG, "NULL argument");
+  if (!(mv->m_ir > 0)) return fail(nullptr, GLASMA_E_ARG, "m_ir must be > 0");
+  if (ns < 1) return fail(nullptr, GLASMA_E_ARG, "ns must be >= 1");
+  const Geom g = geom_of(p);
+  const int ng = p->nc * p->nc - 1;
+  const size_t m = (size_t)ng * g.layer;
+  hipStream_t st = (hipStream_t)stream;
+  double* w = (double*)work;
+  double* phi = w + 2 * m;
+  double* links = w + ic_work_doubles(g, ng);
+  double* partial = links + 2 * (size_t)g.layer * (p->nc == 3 ? 18 : 4);
+  StepConst sc{};
+  sc.a[0] = sc.a[1] = p->a_T;
+  sc.a[2] = p->a_L;
+  sc.dt = p->dt;
+  McvConst k{mv->m_ir, mv->uv_cut, mv->sigma, mv->zA, mv->zB};
+  for (int32_t q = 0; q < ns; ++q) {
+    HIPCHK(nullptr, hipMemcpyAsync(w, rhoT_A + q * m, m * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(nullptr, hipMemcpyAsync(w + m, rhoT_B + q * m, m * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+    launch_ic_phi(w, phi, ng, g, sc, k, st);
+    if (p->nc == 3) launch_bi_sheet<3>(phi, links, g, q == 0, st);
+    else launch_bi_sheet<2>(phi, links, g, q == 0, st);
+  }
+  if (p->nc == 3) launch_bi_fields<3>(links, partial, g, p->a_T, Ez, Bz, out3, st);
+  else launch_bi_fields<2>(links, partial, g, p->a_T, Ez, Bz, out3, st);
+  HIPCHK(nullptr, hipGetLastError());
+  return GLASMA_OK;
+}
+
 // One semi-implicit step: U(t - dt), f1(U(t), U(t - dt)) and the hop once, then fixed-point
 // iterations on E(t + dt/2) until max|dE| <= tol max|E|; the new links end in next_U.
 static int semi_step(glasma_ctx* c, const StepConst& sc) {

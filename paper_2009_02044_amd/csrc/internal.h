@@ -96,6 +96,14 @@ void launch_ic_phi(double* work, double* phi_out, int ng, const Geom& g, const S
 template <typename G, typename T>
 void launch_ic_fields(const double* phi, int ns, T* U, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
                       const McvConst& mv, hipStream_t st);
+// Boost-invariant tau = 0+ fields: work = [initial-condition DFT region | V of both
+// nuclei (2 nt^2 links of double) | block sums]; bi_work_doubles gives its size.
+size_t bi_work_doubles(const Geom& g, int ng, size_t link_doubles);
+template <int NC>
+void launch_bi_sheet(const double* phi, double* work_links, const Geom& g, int first, hipStream_t st);
+template <int NC>
+void launch_bi_fields(const double* work_links, double* partial, const Geom& g, double a_T, double* Ez, double* Bz,
+                      double* out3, hipStream_t st);
 // charges from the (modified) Gauss law: rho = D.(E + scale F2), F2 may be null; split at nz/2
 template <typename G, typename T>
 void launch_gauss_charges(const T* U, const T* E, const T* F2, double scale, T* rhoA, T* rhoB, const Geom& g,

@@ -290,3 +290,35 @@ def host_group_op(nc, fp, op, inp, n_out_per_item):
     out = np.empty((n, n_out_per_item))
     check(lib.glasma_host_group_op(nc, fp, op, n, dptr(inp), dptr(out)))
     return out
+
+
+def boost_invariant_fields(nc, nt, rhoT_A, rhoT_B, a_T=4.0, m_ir=0.2, uv_cut=0.0, device="cuda"):
+    """Boost-invariant Glasma at tau = 0+ of two nuclei (glasma_bi_fields): E_z at the
+    sites and B_z at the plaquette centres, each (n_g, nt, nt) float64 on the device, and
+    the transverse means {"eps0", "EL2_half", "BL2_half"}.  rhoT_*: (n_g, nt, nt) or
+    (ns, n_g, nt, nt) host charges, as for Lattice.init_mv."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU; no device is visible")
+    a = np.ascontiguousarray(rhoT_A, dtype=np.float64)
+    b = np.ascontiguousarray(rhoT_B, dtype=np.float64)
+    if a.shape != b.shape or a.ndim not in (3, 4):
+        raise ValueError("rhoT_A and rhoT_B must both be (n_g, nt, nt) or (ns, n_g, nt, nt)")
+    ns = 1 if a.ndim == 3 else a.shape[0]
+    ng = nc * nc - 1
+    if a.shape[-3:] != (ng, nt, nt):
+        raise ValueError(f"charges must end in ({ng}, {nt}, {nt})")
+    params = _lib.Params(nc, 2, nt, a_T, 1.0, 0.5, 64, 0, 0, 50, 0.0)
+    mv = _lib.MV(m_ir, uv_cut, 1.0, 0.0, 0.0)
+    nbytes = C.c_size_t()
+    check(lib.glasma_bi_work_bytes(C.byref(params), C.byref(nbytes)))
+    dev = _device(device)
+    work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+    Ez = torch.empty((ng, nt, nt), dtype=torch.float64, device=dev)
+    Bz = torch.empty_like(Ez)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    check(lib.glasma_bi_fields(C.byref(params), C.byref(mv), int(ns), dptr(a), dptr(b), C.c_void_p(work.data_ptr()),
+                               C.c_void_p(Ez.data_ptr()), C.c_void_p(Bz.data_ptr()), C.c_void_p(out.data_ptr()),
+                               C.c_void_p(stream.cuda_stream)))
+    o = out.cpu().numpy()
+    return {"Ez": Ez, "Bz": Bz, "eps0": float(o[0]), "EL2_half": float(o[1]), "BL2_half": float(o[2])}
