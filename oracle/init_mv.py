@@ -32,7 +32,9 @@ Steps, in the paper's order:
    ordered product
        V_N = exp(-i lambda_0 phi_{N,0}) exp(-i lambda_1 phi_{N,1}) ... exp(-i lambda_{ns-1} phi_{N,ns-1}),
    the factor of the piece the path crosses later on the right (sheet 0 is the leading
-   edge: B's largest z, A's smallest z).  The order follows from the form
+   edge: B's largest z, A's smallest z).  Sec. 2 defines V^dag as the path-ordered
+   exponential of the field integrated up to x^+-; with later points to the left in
+   V^dag, they stand to the right in V.  The same order follows from the form
    A_i = V d_i V^dag / (ig) of eq. 3d_colorfield_1: inside piece k, V = W e_k with W the
    completed pieces, so d_z A_i = W d_z(e_k d_i e_k^dag) W^dag and the field strength there
    is that of sheet k alone, rotated by W, as gauge covariance of the covariant-gauge

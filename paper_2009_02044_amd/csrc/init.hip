@@ -17,7 +17,8 @@
 //    Sec. 5) the line is the path-ordered product
 //      V_N = exp(-i lambda_0 phi_{N,0}) ... exp(-i lambda_{ns-1} phi_{N,ns-1}),
 //      lambda_k = clamp(ns Lambda_N - k, 0, 1),
-//    the sheet crossed later on the right: with A_i = V d_i V^dag / (ig), the field
+//    the sheet crossed later on the right (V^dag, the path-ordered exponential of
+//    Sec. 2, has later points on the left); with A_i = V d_i V^dag / (ig) the field
 //    strength inside piece k is then sheet k's own, rotated by the completed pieces
 //    (gauge covariance); sheets not reached yet (lambda_k = 0) are 1.
 // 3. U_i = [V_A(x) V_A^dag(x+i)] [V_B(x) V_B^dag(x+i)] (i = x, y), U_z = 1 except the
