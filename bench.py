@@ -231,6 +231,33 @@ def run_bi_limit(sigmas=(8.0, 4.0, 2.0, 1.0)):
     return out
 
 
+def run_rhic_profile(events, m_values=(0.2, 0.4, 0.8), T_fm=2.6):
+    """Rapidity profile of the local rest-frame energy density in the RHIC set-up of Sec. 4
+    (physunits.rhic_setup: SU(2), 2048 x 192^2 cells for a (6 fm)^3 box, sqrt(s) = 200 GeV,
+    Q_s, mu, L, Lambda = 10 GeV from the printed relations): `events` MV events per IR
+    regulator m, event-averaged T^{mu nu} diagonalised per layer on the GPU, eps_loc tau
+    against eta_s in free streaming (physunits.rapidity_profile), Gaussian width sigma_eta."""
+    import synth
+    from paper_2009_02044_amd import physunits as pu
+    out = {"events": events, "T_fm": T_fm, "rows": []}
+    for m in m_values:
+        su = pu.rhic_setup(m_GeV=m)
+        t0 = time.perf_counter()
+        charges = [synth.mv_charges(6000 + 100 * e, 2, su.nt, su.mu, su.a_T) for e in range(events)]
+        r = pu.rapidity_profile(su, charges, T_fm, progress=lambda e, g: print(
+            f"[rhic] m = {m} GeV: event {e + 1}/{events} done, Gauss {g:.1e}", file=sys.stderr, flush=True))
+        wall = time.perf_counter() - t0
+        eta, f = r["eta"], r["eps_loc_tau"]
+        out["rows"].append({"m_GeV": m, "sigma_eta": r["sigma_eta"], "eta_max": float(np.abs(eta).max()),
+                            "sigma_cells": su.sigma, "mu_lat": su.mu, "m_lat": su.m_ir, "a_T": su.a_T,
+                            "steps": r["steps"], "wall_s": wall, "gauss_rel_max": r["gauss_rel_max"],
+                            "profile_eta": [float(x) for x in eta[::16]],
+                            "profile_eps_loc_tau": [float(x) for x in f[::16]]})
+        print(f"[bench] RHIC 200 GeV, m = {m} GeV, {events} events: sigma_eta {r['sigma_eta']:.2f} "
+              f"(|eta| <= {np.abs(eta).max():.2f}), {wall:.1f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def run_batched(steps, warmup, graph_chunk=16):
     """64 events, SU(3) FP32: autotuned tiling, then the timed run; returns throughput and
     the event-averaged T^{mu nu}(z) per N_z class (transverse means averaged over events)."""
@@ -386,6 +413,8 @@ def main():
     ap.add_argument("--no-rest-frame", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
     ap.add_argument("--no-bi-limit", action="store_true")
+    ap.add_argument("--rhic-profile", type=int, default=0,
+                    help="also run the RHIC 200 GeV rapidity-profile study with this many events per m")
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
     ap.add_argument("--precision-steps", type=int, default=2048)
@@ -462,6 +491,8 @@ def main():
                 print(f"[bench] boost-invariant limit, semi-implicit, sigma {row['sigma']:g}: "
                       f"max p_T/eps_0 {row['pT_over_eps0_max']:.3f}, min p_L/eps {row['pL_over_eps_min']:+.3f}",
                       file=sys.stderr, flush=True)
+    if args.rhic_profile > 0:
+        forms["rhic200_rapidity_profile"] = run_rhic_profile(args.rhic_profile)
     if args.precision_study:
         wp = synth.PRECISION_SU3
         forms["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)
