@@ -73,18 +73,19 @@ __device__ __forceinline__ typename G::Link conj_by(const typename G::Link& W, c
   return G::dag_mul(W, G::mul(X, W));
 }
 
-// f1(A, B) for the link (y, d) of slice A: returns -a_d dv(A, B)/dX as components.
-template <typename G, typename T>
+// f1(A, B) for the link (y, d) of slice A: returns -a_d dv(A, B)/dX as components.  The
+// direction is a template argument: each direction's kernel holds only its own terms.
+template <typename G, typename T, int d>
 __device__ typename G::Alg semi_f1(const T* __restrict__ A, const T* __restrict__ B, const Geom& g, Site y,
-                                   int d, const StepConst& c) {
+                                   const StepConst& c) {
   using L = typename G::Link;
   using R = typename G::Real;
   const int64_t Vp = g.Vp;
   L acc = G::zero();
-  if (d < 2) {
+  if constexpr (d < 2) {
     // (x, y) plane: loop C_xy[A] with Y = P(C_xy[B]) at the same base
     const R kxy = (R)(0.5 / (c.a[0] * c.a[0] * c.a[1] * c.a[1]));
-    if (d == 0) {
+    if constexpr (d == 0) {
       {  // factor 0 at base y: +1/2 H
         L C = loop_xy<G, T>(A, g, y), Y = herm_P<G>(loop_xy<G, T>(B, g, y));
         G::add_to(acc, Hf<G>(C, Y), R(0.5) * kxy);
@@ -170,16 +171,15 @@ __device__ __forceinline__ void site_of(const Geom& g, uint32_t s, Site& x) {
   x.z = (int)(s / (uint32_t)g.layer);
 }
 
-// out = f1(Uc, Uo) for every link (direction = blockIdx.y)
-template <typename G, typename T>
+// out = f1(Uc, Uo) for every link of direction d
+template <typename G, typename T, int d>
 __global__ void __launch_bounds__(256) k_semi_f1(const T* __restrict__ Uc, const T* __restrict__ Uo,
                                                  T* __restrict__ out, Geom g, StepConst c) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= (uint32_t)g.V) return;
   Site x;
   site_of<G>(g, s, x);
-  const int d = blockIdx.y;
-  typename G::Alg f = semi_f1<G, T>(Uc, Uo, g, x, d, c);
+  typename G::Alg f = semi_f1<G, T, d>(Uc, Uo, g, x, c);
   store_alg(f, out, d, s, g.Vp);
 }
 
@@ -237,7 +237,7 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
 
 // One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
 // Et <- E'; conv[0] = max |E' - Et_old|, conv[1] = max |E'| (component-wise).
-template <typename G, typename T, bool HOP>
+template <typename G, typename T, bool HOP, int d>
 __global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
                                                    const T* __restrict__ E, const T* __restrict__ F2,
                                                    const T* __restrict__ J, T* __restrict__ Et,
@@ -249,9 +249,8 @@ __global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, con
   if (s < (uint32_t)g.V) {
     Site x;
     site_of<G>(g, s, x);
-    const int d = blockIdx.y;
     const int64_t Vp = g.Vp;
-    A f = semi_f1<G, T>(Uc, Ut_in, g, x, d, c);
+    A f = semi_f1<G, T, d>(Uc, Ut_in, g, x, c);
     A e, f2, eo;
     load_alg(e, E, d, s, Vp);
     load_alg(f2, F2, d, s, Vp);
@@ -259,7 +258,7 @@ __global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, con
     const typename G::Real dt = (typename G::Real)c.dt;
 #pragma unroll
     for (int k = 0; k < G::NG; ++k) e.c[k] += dt * (f.c[k] + f2.c[k]);
-    if (HOP && d == 2) {
+    if constexpr (HOP && d == 2) {
       A j;
       load_alg(j, J, 0, s, Vp);
 #pragma unroll
@@ -294,7 +293,10 @@ __global__ void k_copy_alg(const T* __restrict__ src, T* __restrict__ dst, int64
 template <typename G, typename T>
 void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st) {
   const int bs = 256;
-  hipLaunchKernelGGL((k_semi_f1<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, Uc, Uo, out, g, c);
+  const dim3 grid((unsigned)((g.V + bs - 1) / bs));
+  hipLaunchKernelGGL((k_semi_f1<G, T, 0>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
+  hipLaunchKernelGGL((k_semi_f1<G, T, 1>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
+  hipLaunchKernelGGL((k_semi_f1<G, T, 2>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
 }
 
 template <typename G, typename T>
@@ -315,11 +317,14 @@ template <typename G, typename T>
 void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
                       double* conv, const Geom& g, const StepConst& c, hipStream_t st) {
   const int bs = 256;
-  dim3 grid((unsigned)((g.V + bs - 1) / bs), 3);
+  const dim3 grid((unsigned)((g.V + bs - 1) / bs));
+  // one launch per direction: a kernel holds only that direction's terms
+  hipLaunchKernelGGL((k_semi_iter<G, T, false, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+  hipLaunchKernelGGL((k_semi_iter<G, T, false, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
   if (c.hop)
-    hipLaunchKernelGGL((k_semi_iter<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+    hipLaunchKernelGGL((k_semi_iter<G, T, true, 2>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
   else
-    hipLaunchKernelGGL((k_semi_iter<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+    hipLaunchKernelGGL((k_semi_iter<G, T, false, 2>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
 }
 
 template <typename G, typename T>
