@@ -7,6 +7,11 @@ implementation.
 import ctypes as C
 import os
 
+# torch first: its bundled HIP runtime then carries the soname libglasma.so asks for, so
+# both use one runtime.  Loaded the other way round, the process would hold two HIP
+# runtimes, and device memory from one is invalid in the other.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 # GLASMA_LIB selects another build of the same library (e.g. a tuning variant).
 LIB_PATH = os.environ.get("GLASMA_LIB") or os.path.join(HERE, "libglasma.so")
