@@ -227,6 +227,82 @@ def test_full_size_plain_su3_sampled():
         np.testing.assert_allclose(E_got, E_ref, atol=1e-12 * max(1.0, np.abs(E_ref).max()))
 
 
+class _SampledLinks:
+    """U[i, z, y, x] read on demand from a device array in the C-ABI plain layout
+    (3, r_U, V) and turned into a matrix: lets the oracle's single-site force read a
+    full-size lattice without copying it to the host."""
+
+    def __init__(self, Udev, nc, dims):
+        self.U, self.nc, self.dims = Udev, nc, dims
+        self.shape = (3,) + tuple(dims)
+        self.cache = {}
+
+    def __getitem__(self, key):
+        i, z, y, x = key
+        if key not in self.cache:
+            s = (z * self.dims[1] + y) * self.dims[2] + x
+            c = self.U[i, :, s].cpu().numpy()
+            full = np.zeros((3, c.shape[0], 1))
+            full[i, :, 0] = c
+            from oracle import components
+            self.cache[key] = components.comp_to_links(full, self.nc, (1, 1, 1))[i, 0, 0, 0]
+        return self.cache[key]
+
+
+@pytest.mark.parametrize("fp", [64, 32])
+def test_full_size_precision_workload_sampled(fp):
+    """SU(3) at the precision form's full size, 2048 x 192 x 192 (sigma = 16), FP64 and
+    FP32 (reunitarisation every 8 steps): MV initial state on the GPU, 5 steps, Gauss law and
+    unitarity over the whole lattice, and the E update of the fifth (non-hop) step at
+    sampled sites recomputed by the oracle from the stored links (FP32: the stored FP32
+    values, so the bar is FP32 rounding of the update)."""
+    import torch
+    pkg = lattice_or_skip()
+    w = synth.PRECISION_SU3
+    say("case: full-size precision workload su3 2048x192x192 fp", fp)
+    rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+    lat = new_lattice(pkg, w, fp=fp, reunit_every=8 if fp == 32 else 0)
+    lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma)
+    lat.step(4)
+    o = lat.observables()
+    say("gauss_rel", o["gauss_rel"], "unitarity", o["unitarity"])
+    assert o["gauss_rel"] < (1e-12 if fp == 64 else 1e-5) and o["unitarity"] < (1e-13 if fp == 64 else 1e-5)
+    p = lattice.Params(3, w.a_T, w.a_L, w.dt)
+    assert not lattice.is_hop_step(lat.step_count, p)
+    f = dict(dtype=torch.float64, device=lat.device)
+    U0 = torch.empty(3, lat.r, lat.V, **f)
+    E0 = torch.empty(3, lat.ng, lat.V, **f)
+    from paper_2009_02044_amd._lib import lib
+    import ctypes as C
+    lat._chk(lib.glasma_get_state_device(lat.ctx, C.c_void_p(U0.data_ptr()), C.c_void_p(E0.data_ptr()), None, None))
+    lat.step(1)
+    E1 = torch.empty(3, lat.ng, lat.V, **f)
+    lat._chk(lib.glasma_get_state_device(lat.ctx, None, C.c_void_p(E1.data_ptr()), None, None))
+    # the field scale: sites far from the nuclei carry exponentially small E whose
+    # digits are rounding noise on either side (bar as max(|ref|, RMS of the field))
+    rms = float(torch.sqrt(torch.mean(E1 * E1)))
+    torch.cuda.synchronize()
+    dims = (w.nz, w.nt, w.nt)
+    Us = _SampledLinks(U0, 3, dims)
+    g = synth.rng(11)
+    sites = [(int(g.integers(w.nz)), int(g.integers(w.nt)), int(g.integers(w.nt))) for _ in range(16)]
+    sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 7, w.nt - 1), (3 * w.nz // 4, 0, 100)]
+    from oracle import su
+    worst = 0.0
+    for (z, y, x) in sites:
+        s = (z * w.nt + y) * w.nt + x
+        F = lattice.force_at_site(Us, p.a, (z, y, x))
+        E_ref = su.from_components(E0[:, :, s].cpu().numpy(), 3) + p.dt * F
+        E_got = su.from_components(E1[:, :, s].cpu().numpy(), 3)
+        scale = max(np.abs(E_ref).max(), rms)
+        err = np.abs(E_got - E_ref).max() / scale
+        worst = max(worst, err)
+        # FP32: the force sums ~100 products of O(1) link entries in FP32 (unit roundoff
+        # 6e-8) while E is small on most of the lattice (RMS ~ 1/4 of the peak)
+        assert err < (1e-10 if fp == 64 else 5e-5), ((z, y, x), err)
+    say("worst sampled E-update error (relative to max(|E|, RMS E))", worst)
+
+
 @pytest.mark.parametrize("nc,nz,nt", [(3, 3, 64), (3, 4, 32), (2, 4, 16), (3, 4, 12)])
 def test_leapfrog_generic_state_row_layouts(nc, nz, nt):
     """Per-component parity on a generic state (random links and fields, charges from the
