@@ -53,19 +53,23 @@ template <typename G>
 __device__ __forceinline__ typename G::Link herm_P(const typename G::Link& C) {
   return G::herm_from_alg(G::proj(C));
 }
-// C Y + Y C^dag
+// M + M^dag for a product M of a loop and a hermitian Y.  SU(3) carries a hermitian X as X
+// itself; SU(2) carries it as i X (a quaternion), where the same sum reads M - M^dag.
 template <typename G>
-__device__ __forceinline__ typename G::Link Hf(const typename G::Link& C, const typename G::Link& Y) {
-  typename G::Link h = G::mul(C, Y);
-  G::add_to(h, G::mul_dag(Y, C), (typename G::Real)1);
+__device__ __forceinline__ typename G::Link herm_sum(const typename G::Link& m) {
+  typename G::Link h = m;
+  G::add_to(h, G::dag(m), (typename G::Real)(G::NC == 3 ? 1 : -1));
   return h;
 }
-// Y C + C^dag Y  (= C^dag H C)
+// C Y + Y C^dag = M + M^dag with M = C Y (Y hermitian): one product instead of two
+template <typename G>
+__device__ __forceinline__ typename G::Link Hf(const typename G::Link& C, const typename G::Link& Y) {
+  return herm_sum<G>(G::mul(C, Y));
+}
+// Y C + C^dag Y  (= C^dag H C) = N + N^dag with N = Y C
 template <typename G>
 __device__ __forceinline__ typename G::Link Hb(const typename G::Link& C, const typename G::Link& Y) {
-  typename G::Link h = G::mul(Y, C);
-  G::add_to(h, G::dag_mul(C, Y), (typename G::Real)1);
-  return h;
+  return herm_sum<G>(G::mul(Y, C));
 }
 // W^dag X W
 template <typename G>
@@ -238,11 +242,11 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
 // One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
 // Et <- E'; conv[0] = max |E' - Et_old|, conv[1] = max |E'| (component-wise).
 template <typename G, typename T, bool HOP, int d>
-__global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
-                                                   const T* __restrict__ E, const T* __restrict__ F2,
-                                                   const T* __restrict__ J, T* __restrict__ Et,
-                                                   T* __restrict__ Ut_out, double* __restrict__ conv, Geom g,
-                                                   StepConst c) {
+__device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
+                                               const T* __restrict__ E, const T* __restrict__ F2,
+                                               const T* __restrict__ J, T* __restrict__ Et,
+                                               T* __restrict__ Ut_out, double* __restrict__ conv, const Geom& g,
+                                               const StepConst& c) {
   using A = typename G::Alg;
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   double dmax = 0.0, emax = 0.0;
@@ -283,6 +287,23 @@ __global__ void __launch_bounds__(256) k_semi_iter(const T* __restrict__ Uc, con
     atomic_max_nonneg(conv + 1, emax);
   }
 }
+// Transverse links: held to two waves per SIMD (a few bytes of spill, against one wave
+// without the bound); the longitudinal link's terms need more registers than that allows.
+template <typename G, typename T, int d>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_semi_iter_t(const T* __restrict__ Uc, const T* __restrict__ Ut_in, const T* __restrict__ E,
+              const T* __restrict__ F2, const T* __restrict__ J, T* __restrict__ Et, T* __restrict__ Ut_out,
+              double* __restrict__ conv, Geom g, StepConst c) {
+  semi_iter_body<G, T, false, d>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+}
+template <typename G, typename T, bool HOP>
+__global__ void __launch_bounds__(256) k_semi_iter_z(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
+                                                     const T* __restrict__ E, const T* __restrict__ F2,
+                                                     const T* __restrict__ J, T* __restrict__ Et,
+                                                     T* __restrict__ Ut_out, double* __restrict__ conv, Geom g,
+                                                     StepConst c) {
+  semi_iter_body<G, T, HOP, 2>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+}
 
 template <typename G, typename T>
 __global__ void k_copy_alg(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
@@ -319,12 +340,12 @@ void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, cons
   const int bs = 256;
   const dim3 grid((unsigned)((g.V + bs - 1) / bs));
   // one launch per direction: a kernel holds only that direction's terms
-  hipLaunchKernelGGL((k_semi_iter<G, T, false, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
-  hipLaunchKernelGGL((k_semi_iter<G, T, false, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
   if (c.hop)
-    hipLaunchKernelGGL((k_semi_iter<G, T, true, 2>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+    hipLaunchKernelGGL((k_semi_iter_z<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
   else
-    hipLaunchKernelGGL((k_semi_iter<G, T, false, 2>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
+    hipLaunchKernelGGL((k_semi_iter_z<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c);
 }
 
 template <typename G, typename T>
