@@ -430,7 +430,7 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import synth
     w = synth.PLAIN_SU3
