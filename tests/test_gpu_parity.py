@@ -303,12 +303,15 @@ def test_full_size_precision_workload_sampled(fp):
     say("worst sampled E-update error (relative to max(|E|, RMS E))", worst)
 
 
-@pytest.mark.parametrize("nc,nz,nt", [(3, 3, 64), (3, 4, 32), (2, 4, 16), (3, 4, 12)])
+@pytest.mark.parametrize("nc,nz,nt", [(3, 3, 64), (3, 4, 32), (2, 4, 16), (3, 4, 12), (3, 2, 2), (2, 2, 3),
+                                      (3, 5, 2), (3, 2, 65)])
 def test_leapfrog_generic_state_row_layouts(nc, nz, nt):
     """Per-component parity on a generic state (random links and fields, charges from the
     Gauss law) for rows of 64, 32 and 16 sites (a wavefront holds whole rows: x neighbours
     come from adjacent lanes, backward -x plaquettes from the neighbour lane) and of 12
-    sites (rows cross wavefronts: every neighbour from memory); steps 1..6 include hops."""
+    sites (rows cross wavefronts: every neighbour from memory); the smallest lattices (two
+    sites per row: x + 1 and x - 1 are the same site; nz = 2: z + 1 = z - 1) and a row of
+    65 (one lane past a wavefront); steps 1..6 include hops."""
     pkg = lattice_or_skip()
     say(f"case: generic state su{nc} {nz}x{nt}x{nt}")
     dims = (nz, nt, nt)
