@@ -400,3 +400,38 @@ def test_step_observe_equals_step_then_observe(nc, nz, nt, fp):
     sa, sb = a.get_state(), b.get_state()
     for k in ("U", "E", "rhoA", "rhoB"):
         assert np.array_equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("nc,fp", [(3, 64), (2, 64), (3, 32)])
+def test_gauge_invariance_of_the_gpu_evolution(nc, fp):
+    """A random gauge transformation of the initial state (links, E and charges) leaves the
+    GPU's T^{mu nu} slices, H and Gauss residual unchanged, at the start and after 6 steps
+    through charge hops: the update and the CPIC hop are gauge covariant on the GPU too."""
+    pkg = lattice_or_skip()
+    nz, nt = 8, 16
+    say(f"case: gauge invariance su{nc} {nz}x{nt}x{nt} fp{fp}")
+    dims = (nz, nt, nt)
+    ng = nc * nc - 1
+    p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=0.5)
+    st = init_mv.state_from_algebra(synth.normal(71, (3,) + dims + (ng,), 0.5),
+                                    synth.normal(72, (3,) + dims + (ng,), 0.3), p)
+    from oracle import su
+    Omega = su.expi(su.from_components(synth.normal(73, dims + (ng,), 1.5), nc))
+    st2 = lattice.gauge_transform(st, Omega)
+    lats = []
+    for s_ in (st, st2):
+        lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=0.5, fp=fp)
+        lat.init_state(*to_comp(s_), step0=0)
+        lats.append(lat)
+    tol = 1e-11 if fp == 64 else 2e-5
+    for n in (0, 6):
+        if n:
+            for lat in lats:
+                lat.step(n)
+        o1, o2 = lats[0].observables(), lats[1].observables()
+        scale = np.abs(o1["tmunu_z"]).max(axis=1, keepdims=True)
+        err = np.max(np.abs(o1["tmunu_z"] - o2["tmunu_z"]) / scale)
+        err_H = abs(o1["energy"] - o2["energy"]) / abs(o1["energy"])
+        say(f"  after {n} steps: slices {err:.1e}, H {err_H:.1e}, gauss {o1['gauss_rel']:.1e} {o2['gauss_rel']:.1e}")
+        assert err < tol and err_H < tol
+        assert o2["gauss_rel"] < (1e-12 if fp == 64 else 1e-5)
