@@ -471,3 +471,41 @@ def test_energy_conservation_in_free_evolution():
     # start E(-dt/2) = 0 differs between the two runs) and does not drift
     assert fl[0.25] < 0.6 * fl[0.5]
     assert dr[0.5] < 0.1 * fl[0.5] and dr[0.25] < 0.1 * fl[0.25]
+
+
+@pytest.mark.parametrize("nt,k", [(8, (0, 1, 2)), (8, (0, 3, 1)), (12, (0, 2, 3))])
+def test_dispersion_relation_of_small_plane_waves(nt, k):
+    """A small single-colour plane wave A_x ~ cos(k.x) on the GPU: its linearised leapfrog
+    evolution obeys A(t+dt) + A(t-dt) = 2 cos(w dt) A(t) with the lattice dispersion
+    (2/dt)^2 sin^2(w dt/2) = sum_i (2/a_i)^2 sin^2(k_i a_i/2) (closed form; rows of 8 sites
+    take the lane-exchange path, rows of 12 the memory path)."""
+    pkg = lattice_or_skip()
+    from oracle import su
+    nc, nz, a_T, dt = 2, 16, 4.0, 0.5
+    say(f"case: dispersion nt {nt} k {k}")
+    dims = (nz, nt, nt)
+    a = (a_T, a_T, 1.0)
+    p = lattice.Params(nc=nc, a_T=a_T, a_L=1.0, dt=dt)
+    nx = np.arange(nt)[None, None, :]
+    ny = np.arange(nt)[None, :, None]
+    nzv = np.arange(nz)[:, None, None]
+    kv = [2 * np.pi * k[0] / nt, 2 * np.pi * k[1] / nt, 2 * np.pi * k[2] / nz]
+    phase = kv[0] * nx + kv[1] * ny + kv[2] * nzv
+    alg = np.zeros((3,) + dims + (3,))
+    alg[0, ..., 2] = a[0] * 1e-6 * np.cos(phase)        # polarisation x, k has no x part
+    z = np.zeros(dims + (2, 2), complex)
+    st = lattice.State(su.expi(su.from_components(alg, nc)), np.zeros((3,) + dims + (2, 2), complex), z, z.copy(), 0, p)
+    lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=a_T, a_L=1.0, dt=dt, fp=64)
+    lat.init_state(*to_comp(st), step0=0)
+    A = []
+    for _ in range(4):
+        g = from_comp(lat.get_state(), nc, dims, p)
+        A.append(su.to_components(su.logi(g.U[0]))[..., 2])
+        lat.step(1)
+    A = np.array(A)
+    msk = np.abs(A[1]) > 0.3 * np.abs(A[1]).max()
+    cos_w = ((A[2] + A[0]) / (2 * A[1]))[msk]
+    Om2 = sum((2 / a[i]) ** 2 * np.sin(kv[i] / 2) ** 2 for i in range(3))
+    expect = 1 - dt ** 2 * Om2 / 2
+    say("  cos(w dt)", float(np.mean(cos_w)), "closed form", expect, "max dev", float(np.abs(cos_w - expect).max()))
+    np.testing.assert_allclose(cos_w, expect, rtol=1e-8, atol=1e-9)
