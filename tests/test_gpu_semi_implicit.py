@@ -87,3 +87,45 @@ def test_semi_implicit_fp32_against_fp64_oracle(nc):
     err = np.max(np.abs(go["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True))
     say(" T^{mu nu} slices", err)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("k,dt", [((0, 0, 3), 1.0), ((0, 0, 7), 1.0), ((2, 0, 5), 1.0), ((3, 0, 6), 0.5)])
+def test_semi_implicit_dispersion_on_the_gpu(k, dt):
+    """A small y-polarised single-colour wave with k = (k_x, 0, k_z) under the GPU's
+    semi-implicit scheme: A(t+dt) + A(t-dt) = 2 cos(w dt) A(t) with the closed form
+    cos(w dt) = (1 - dt^2 K_z / 2) / (1 + dt^2 K_x / 2), K_i = (2/a_i)^2 sin^2(k_i a_i / 2);
+    at k_x = 0 and dt = a_L, w = k_z: no dispersion along the beam axis."""
+    pkg = lattice_or_skip()
+    from oracle import su
+    nc, nz, nt = 2, 16, 8
+    say(f"case: semi-implicit dispersion k {k} dt {dt}")
+    dims = (nz, nt, nt)
+    a = (4.0, 4.0, 1.0)
+    p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=dt)
+    nx = np.arange(nt)[None, None, :]
+    nzv = np.arange(nz)[:, None, None]
+    phase = 2 * np.pi * (k[0] * nx / nt + k[2] * nzv / nz) + np.zeros(dims)
+    alg = np.zeros((3,) + dims + (3,))
+    alg[1, ..., 2] = a[1] * 1e-6 * np.cos(phase)
+    U = su.expi(su.from_components(alg, nc))
+    z = np.zeros(dims + (2, 2), complex)
+    st = lattice.State(U, np.zeros_like(U), z, z.copy(), 0, p)
+    lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=dt, fp=64, scheme=1, max_iter=100, tol=1e-15)
+    lat.init_state(*to_comp(st), step0=0)
+    A = []
+    for _ in range(4):
+        g = from_comp(lat.get_state(), nc, dims, p)
+        A.append(su.to_components(su.logi(g.U[1]))[..., 2])
+        lat.step(1)
+    A = np.array(A)
+    kx, kz = 2 * np.pi * k[0] / nt, 2 * np.pi * k[2] / nz
+    Kx = (2 / a[0]) ** 2 * np.sin(kx / 2) ** 2
+    Kz = (2 / a[2]) ** 2 * np.sin(kz / 2) ** 2
+    expect = (1 - dt ** 2 * Kz / 2) / (1 + dt ** 2 * Kx / 2)
+    for n in (1, 2):
+        msk = np.abs(A[n]) > 0.3 * np.abs(A[n]).max()
+        got = ((A[n + 1] + A[n - 1]) / (2 * A[n]))[msk]
+        say(f"  n {n}: cos(w dt) {float(np.mean(got)):.12f} closed form {expect:.12f}")
+        np.testing.assert_allclose(got, expect, rtol=1e-7, atol=1e-8)
+    if k[0] == 0 and dt == 1.0:
+        assert abs(np.arccos(expect) - kz) < 1e-12
