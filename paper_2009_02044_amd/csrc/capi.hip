@@ -29,6 +29,7 @@ struct glasma_ctx {
   int last_iters;     // iterations of the last semi-implicit step
   // differentiation form: checkpoints written by glasma_adjoint_forward
   bool adj_ok;
+  bool semi_prev;     // semi-implicit: E of the previous step kept (starting guess of the solve)
   int64_t adj_s0;
   int32_t adj_steps, adj_every;
   int adj_off0;
@@ -99,9 +100,10 @@ static Geom geom_of(const glasma_params* p) {
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Work buffer: [general region: initial conditions or observable reductions]
-// then, for the semi-implicit scheme, [U(t-dt) | trial links | trial E | f1(U(t), U(t-dt)) | dt j | 2 doubles].
+// then, for the semi-implicit scheme, [U(t-dt) | trial links | trial E | f1(U(t), U(t-dt)) | dt j |
+// E of the previous step | 2 doubles].
 struct SemiRegion {
-  size_t up, ut, et, f2, j, conv, end;  // byte offsets
+  size_t up, ut, et, f2, j, ep, conv, end;  // byte offsets
 };
 static size_t general_bytes(const glasma_params* p) {
   Geom g = geom_of(p);
@@ -122,7 +124,8 @@ static SemiRegion semi_region(const glasma_params* p) {
   s.et = s.ut + align256(3 * (size_t)r * g.Vp * e);
   s.f2 = s.et + align256(3 * (size_t)ng * g.Vp * e);
   s.j = s.f2 + align256(3 * (size_t)ng * g.Vp * e);
-  s.conv = s.j + align256((size_t)ng * g.Vp * e);
+  s.ep = s.j + align256((size_t)ng * g.Vp * e);
+  s.conv = s.ep + align256(3 * (size_t)ng * g.Vp * e);
   s.end = s.conv + 256;
   return s;
 }
@@ -256,6 +259,7 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
   c->offA = c->offB = 0;
   c->step = step0;
   c->ready = true;
+  c->semi_prev = false;
   c->adj_ok = false;
   return GLASMA_OK;
 }
@@ -291,7 +295,8 @@ int glasma_init_mv_sheets(glasma_ctx* c, const glasma_mv* mv, int32_t ns, const 
       // charges that make the conserved combination D.(E + dt f1(U(t0), U(t0 - dt))) - rho vanish
       const SemiRegion r = semi_region(&c->p);
       char* w = (char*)c->b.work;
-      launch_semi_begin<G, T>((T*)c->b.U, (T*)c->b.E, (T*)(w + r.up), (T*)(w + r.ut), (T*)(w + r.et), c->g, sc,
+      launch_semi_begin<G, T>((T*)c->b.U, (T*)c->b.E, (const T*)nullptr, (const T*)nullptr, (T*)(w + r.up),
+                              (T*)(w + r.ut), (T*)(w + r.et), c->g, sc,
                               c->stream);
       launch_semi_f1<G, T>((T*)c->b.U, (T*)(w + r.up), (T*)(w + r.f2), c->g, sc, c->stream);
       launch_gauss_charges<G, T>((T*)c->b.U, (T*)c->b.E, (T*)(w + r.f2), c->p.dt, (T*)c->b.rhoA,
@@ -301,6 +306,7 @@ int glasma_init_mv_sheets(glasma_ctx* c, const glasma_mv* mv, int32_t ns, const 
   });
   HIPCHK(c, hipGetLastError());
   c->ready = true;
+  c->semi_prev = false;
   return GLASMA_OK;
 }
 
@@ -368,8 +374,11 @@ static int semi_step(glasma_ctx* c, const StepConst& sc) {
     T* Et = (T*)(w + r.et);
     T* F2 = (T*)(w + r.f2);
     T* J = (T*)(w + r.j);
-    launch_semi_begin<G, T>(Uc, (T*)c->b.E, Up, Un, Et, c->g, sc, c->stream);
+    T* Ep = (T*)(w + r.ep);
+    // the hop first: its current enters the starting guess
     if (sc.hop) launch_semi_hop<G, T>(Uc, (T*)c->b.rhoA, (T*)c->b.rhoB, J, c->g, sc, c->stream);
+    launch_semi_begin<G, T>(Uc, (T*)c->b.E, c->semi_prev ? Ep : nullptr, sc.hop ? J : nullptr, Up, Un, Et, c->g,
+                            sc, c->stream);
     launch_semi_f1<G, T>(Uc, Up, F2, c->g, sc, c->stream);
     T* in = Un;
     T* out = Ub;
@@ -388,7 +397,9 @@ static int semi_step(glasma_ctx* c, const StepConst& sc) {
     if (!ok) return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");
     const int64_t nl = 3 * (int64_t)c->rs * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
     if (in != Un) launch_copy<G, T>(in, Un, nl, c->stream);
+    launch_semi_keep<G, T>((T*)c->b.E, sc.hop ? J : nullptr, Ep, c->g, c->stream);
     launch_copy<G, T>(Et, (T*)c->b.E, ne, c->stream);
+    c->semi_prev = true;
     return GLASMA_OK;
   });
 }
@@ -1163,6 +1174,7 @@ int glasma_set_state_device(glasma_ctx* c, const double* U, const double* E, con
   c->offA = c->offB = 0;
   c->step = step0;
   c->ready = true;
+  c->semi_prev = false;
   c->adj_ok = false;
   return GLASMA_OK;
 }

@@ -72,8 +72,10 @@ void launch_reunit(T* U, const Geom& g, hipStream_t st);
 template <typename G, typename T>
 void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st);
 template <typename G, typename T>
-void launch_semi_begin(const T* U, const T* E, T* Up, T* Ut, T* Et, const Geom& g, const StepConst& c,
-                       hipStream_t st);
+void launch_semi_begin(const T* U, const T* E, const T* Ep, const T* J, T* Up, T* Ut, T* Et, const Geom& g,
+                       const StepConst& c, hipStream_t st);
+template <typename G, typename T>
+void launch_semi_keep(const T* E, const T* J, T* Ep, const Geom& g, hipStream_t st);
 template <typename G, typename T>
 void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, const Geom& g, const StepConst& c, hipStream_t st);
 template <typename G, typename T>

@@ -188,22 +188,59 @@ __global__ void __launch_bounds__(256) k_semi_f1(const T* __restrict__ Uc, const
 }
 
 // U(t-dt) = exp(-i a dt E) U(t) into Up, first trial U(t+dt) = exp(+i a dt E) U(t) into Ut,
-// first trial E(t+dt/2) = E(t-dt/2) into Et
+// first trial E(t+dt/2) into Et and U(t+dt) = exp(+i a dt Et) U(t) into Ut.  With the
+// previous step at hand, Ep = E(t-3dt/2) + dt j(t-dt) (k_semi_keep), so E - Ep is the last
+// step's field increment without its current: the trial is E + (E - Ep) + dt j(t) (the
+// current of this step, J, on hop steps), else E(t-dt/2) (+ dt j).  Only the starting point
+// of the iteration; its fixed point is the same.
 template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_semi_begin(const T* __restrict__ U, const T* __restrict__ E,
+                                                    const T* __restrict__ Ep, const T* __restrict__ J,
                                                     T* __restrict__ Up, T* __restrict__ Ut, T* __restrict__ Et,
                                                     Geom g, StepConst c) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= (uint32_t)g.V) return;
   const int d = blockIdx.y;
   typename G::Link u;
-  typename G::Alg e;
+  typename G::Alg e, et;
   load_link(u, U, d, s, g.Vp);
   load_alg(e, E, d, s, g.Vp);
+  et = e;
+  if (Ep) {
+    typename G::Alg ep;
+    load_alg(ep, Ep, d, s, g.Vp);
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) et.c[k] = e.c[k] + (e.c[k] - ep.c[k]);
+  }
+  if (J && d == 2) {
+    typename G::Alg j;
+    load_alg(j, J, 0, s, g.Vp);
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) et.c[k] += j.c[k];
+  }
   const typename G::Real k = (typename G::Real)(c.a[d] * c.dt);
   store_link(G::mul(G::expi(e, -k), u), Up, d, s, g.Vp);
-  store_link(G::mul(G::expi(e, k), u), Ut, d, s, g.Vp);
-  store_alg(e, Et, d, s, g.Vp);
+  store_link(G::mul(G::expi(et, k), u), Ut, d, s, g.Vp);
+  store_alg(et, Et, d, s, g.Vp);
+}
+
+// after a step: Ep = E(t-dt/2) + [z] dt j(t) (J on hop steps), the reference of the next
+// step's starting guess
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_semi_keep(const T* __restrict__ E, const T* __restrict__ J,
+                                                   T* __restrict__ Ep, Geom g) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  const int d = blockIdx.y;
+  typename G::Alg e;
+  load_alg(e, E, d, s, g.Vp);
+  if (J && d == 2) {
+    typename G::Alg j;
+    load_alg(j, J, 0, s, g.Vp);
+#pragma unroll
+    for (int k = 0; k < G::NG; ++k) e.c[k] += j.c[k];
+  }
+  store_alg(e, Ep, d, s, g.Vp);
 }
 
 // hop of both charge populations with the links U(t) and the current dt j_z = a_L (rho_A' - rho_B)
@@ -321,11 +358,17 @@ void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepC
 }
 
 template <typename G, typename T>
-void launch_semi_begin(const T* U, const T* E, T* Up, T* Ut, T* Et, const Geom& g, const StepConst& c,
-                       hipStream_t st) {
+void launch_semi_begin(const T* U, const T* E, const T* Ep, const T* J, T* Up, T* Ut, T* Et, const Geom& g,
+                       const StepConst& c, hipStream_t st) {
   const int bs = 256;
-  hipLaunchKernelGGL((k_semi_begin<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, U, E, Up, Ut, Et,
-                     g, c);
+  hipLaunchKernelGGL((k_semi_begin<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, U, E, Ep, J,
+                     Up, Ut, Et, g, c);
+}
+
+template <typename G, typename T>
+void launch_semi_keep(const T* E, const T* J, T* Ep, const Geom& g, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_semi_keep<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, E, J, Ep, g);
 }
 
 template <typename G, typename T>
@@ -356,7 +399,9 @@ void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 
 #define GL_SEMI_INST(G, T)                                                                                      \
   template void launch_semi_f1<G, T>(const T*, const T*, T*, const Geom&, const StepConst&, hipStream_t);      \
-  template void launch_semi_begin<G, T>(const T*, const T*, T*, T*, T*, const Geom&, const StepConst&,         \
+  template void launch_semi_keep<G, T>(const T*, const T*, T*, const Geom&, hipStream_t);                    \
+  template void launch_semi_begin<G, T>(const T*, const T*, const T*, const T*, T*, T*, T*, const Geom&,        \
+                                        const StepConst&, \
                                         hipStream_t);                                                          \
   template void launch_semi_hop<G, T>(const T*, T*, T*, T*, const Geom&, const StepConst&, hipStream_t);       \
   template void launch_semi_iter<G, T>(const T*, const T*, const T*, const T*, const T*, T*, T*, double*,      \
