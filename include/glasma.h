@@ -172,7 +172,11 @@ int glasma_bi_fields(const glasma_params* p, const glasma_mv* mv, int32_t ns, co
 
 /* Advance n >= 0 steps (leapfrog or semi-implicit per params, CPIC hops on the steps
  * the schedule S(s) = floor((s + 1/2) dt/a_L + 1/2) advances, reunitarisation every
- * reunit_every steps when set).  Asynchronous for the leapfrog. */
+ * reunit_every steps when set).  Asynchronous for the leapfrog.  The semi-implicit step
+ * iterates its fixed point (under-relaxed) until max|dE| <= tol max|E|, from a start
+ * extrapolated from the previous step when the context made that step; after a state
+ * upload it starts from E, so a resumed run agrees with an uninterrupted one to tol.
+ * GLASMA_E_NOCONV after max_iter iterations, GLASMA_E_NONFINITE on a non-finite field. */
 int glasma_step(glasma_ctx* ctx, int32_t n);
 
 /* Current j (device, 3 * n_g * V reals of the context's precision, in the plain host
