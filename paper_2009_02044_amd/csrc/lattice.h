@@ -86,19 +86,34 @@ template <typename S> struct Vec16;
 template <> struct Vec16<float> { using type = float4; };
 template <> struct Vec16<double> { using type = double2; };
 
-// load / store the W components of site s from one direction's record array
-template <typename T, typename S, int W>
+template <typename S> struct NVec16;
+template <> struct NVec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NVec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// load / store the W components of site s from one direction's record array.  NT marks
+// the loads non-temporal: for fields that only the site's own thread reads (E, the
+// charges), so that they leave the L2 to the links the neighbours still read.
+#ifndef GL_NT_LOAD
+#define GL_NT_LOAD 1
+#endif
+template <typename T, typename S, int W, bool NT = false>
 GL_HD void load_comps(T (&v)[W], const S* __restrict__ dir, uint32_t s) {
   using Sh = RecShape<S, W>;
-  using V16 = typename Vec16<S>::type;
+  using NV = typename NVec16<S>::type;
   const char* rec = (const char*)dir + (uint64_t)(s / RB) * Sh::BYTES;
   const uint32_t l = s % RB;
 #pragma unroll
   for (int q = 0; q < Sh::NF; ++q) {
-    const V16 x = *(const V16*)(rec + q * (RB * 16) + l * 16);
-    const S* e = (const S*)&x;
+    const NV* src = (const NV*)(rec + q * (RB * 16) + l * 16);
+    NV x;
+#if GL_NT_LOAD && defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (NT) x = __builtin_nontemporal_load(src);
+    else x = *src;
+#else
+    x = *src;
+#endif
 #pragma unroll
-    for (int k = 0; k < Sh::VW; ++k) v[q * Sh::VW + k] = (T)e[k];
+    for (int k = 0; k < Sh::VW; ++k) v[q * Sh::VW + k] = (T)x[k];
   }
   if constexpr (Sh::TL > 0) {
     const S* t = (const S*)(rec + Sh::NF * (RB * 16) + l * (Sh::TL * sizeof(S)));
@@ -112,9 +127,6 @@ GL_HD void load_comps(T (&v)[W], const S* __restrict__ dir, uint32_t s) {
 #ifndef GL_NT_STORE
 #define GL_NT_STORE 1
 #endif
-template <typename S> struct NVec16;
-template <> struct NVec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
-template <> struct NVec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <typename T, typename S, int W>
 GL_HD void store_comps(const T (&v)[W], S* __restrict__ dir, uint32_t s) {
   using Sh = RecShape<S, W>;
@@ -222,6 +234,12 @@ template <typename A, typename S>
 GL_HD void load_alg(A& a, const S* __restrict__ f, int i, uint32_t s, int64_t Vp) {
   constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
   load_comps<decltype(a.c[0] + 0), S, NG>(a.c, field_dir(f, i, NG, Vp), s);
+}
+// the same for a field only the site's own thread reads (non-temporal loads)
+template <typename A, typename S>
+GL_HD void load_alg_own(A& a, const S* __restrict__ f, int i, uint32_t s, int64_t Vp) {
+  constexpr int NG = sizeof(a.c) / sizeof(a.c[0]);
+  load_comps<decltype(a.c[0] + 0), S, NG, true>(a.c, field_dir(f, i, NG, Vp), s);
 }
 template <typename A, typename S>
 GL_HD void store_alg(const A& a, S* __restrict__ f, int i, uint32_t s, int64_t Vp) {

@@ -258,8 +258,8 @@ __global__ void __launch_bounds__(256) k_semi_hop(const T* __restrict__ U, T* __
   const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
   const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
   A rb, ra;
-  load_alg(rb, rhoB, 0, sB, Vp);
-  load_alg(ra, rhoA, 0, sA, Vp);
+  load_alg_own(rb, rhoB, 0, sB, Vp);
+  load_alg_own(ra, rhoA, 0, sA, Vp);
   A rbn = G::transport(Uz, rb);
   A ran = G::transport_inv(Uz, ra);
   store_alg(rbn, rhoB, 0, sB, Vp);
@@ -293,15 +293,15 @@ __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T
     const int64_t Vp = g.Vp;
     A f = semi_f1<G, T, d>(Uc, Ut_in, g, x, c);
     A e, f2, eo;
-    load_alg(e, E, d, s, Vp);
-    load_alg(f2, F2, d, s, Vp);
-    load_alg(eo, Et, d, s, Vp);
+    load_alg_own(e, E, d, s, Vp);
+    load_alg_own(f2, F2, d, s, Vp);
+    load_alg_own(eo, Et, d, s, Vp);
     const typename G::Real dt = (typename G::Real)c.dt;
 #pragma unroll
     for (int k = 0; k < G::NG; ++k) e.c[k] += dt * (f.c[k] + f2.c[k]);
     if constexpr (HOP && d == 2) {
       A j;
-      load_alg(j, J, 0, s, Vp);
+      load_alg_own(j, J, 0, s, Vp);
 #pragma unroll
       for (int k = 0; k < G::NG; ++k) e.c[k] += j.c[k];
     }

@@ -57,7 +57,7 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
   // i is a run-time value: select the spacing (no indexed local array)
   const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
   A e;
-  load_alg(e, E, i, s, Vp);
+  load_alg_own(e, E, i, s, Vp);
   A eo;
   if constexpr (OBS) eo = e;
   const T kf = (T)(-c.dt / ai);
@@ -67,8 +67,8 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
     const uint32_t sB = site_index(g, x.x, x.y, slotB(x.z, c.offB, g.nz));
     const uint32_t sA = site_index(g, x.x, x.y, slotA(wrap_add(x.z, 1, g.nz), c.offA, g.nz));
     A rb, ra;
-    load_alg(rb, rhoB, 0, sB, Vp);
-    load_alg(ra, rhoA, 0, sA, Vp);
+    load_alg_own(rb, rhoB, 0, sB, Vp);
+    load_alg_own(ra, rhoA, 0, sA, Vp);
     A rbn = G::transport(Ui, rb);
     A ran = G::transport_inv(Ui, ra);
     store_alg(rbn, rhoB, 0, sB, Vp);
