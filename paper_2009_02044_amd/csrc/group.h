@@ -78,6 +78,10 @@ template <typename T> struct Su2 {
   }
   // proj(a b^dag)
   static GL_HD Alg proj_mul_dag(const Link& a, const Link& b) { return proj_mul(a, dag(b)); }
+  static GL_HD Alg proj_retr_mul_dag(const Link& a, const Link& b, T& tr) {
+    tr = retr_mul_dag(a, b);
+    return proj_mul_dag(a, b);
+  }
   // exp(i s X), X = x.s/2: cos(|sx|/2) + i sin(|sx|/2) n.s
   static GL_HD Link expi(const Alg& x, T s) {
     T v0 = s * x.c[0], v1 = s * x.c[1], v2 = s * x.c[2];
@@ -283,8 +287,9 @@ template <typename T> struct Su3 {
   static GL_HD void bent(const Link& b, int k, int j, T& r, T& i) {
     if (DAG) { r = b.re[j][k]; i = -b.im[j][k]; } else { r = b.re[k][j]; i = b.im[k][j]; }
   }
+  // With tr given, also Re Tr M (the real diagonal, from the same products).
   template <bool DAG>
-  static GL_HD Alg proj_prod(const Link& a, const Link& b) {
+  static GL_HD Alg proj_prod(const Link& a, const Link& b, T* tr = nullptr) {
     const T is3 = T(0.57735026918962576451);
     // Im M_pq + Im M_qp and Re M_pq - Re M_qp for the pairs (0,1), (0,2), (1,2)
     T sym[3], asym[3];
@@ -310,19 +315,25 @@ template <typename T> struct Su3 {
       }
       sym[n] = y; asym[n] = z;
     }
-    T di[3];
+    T di[3], dr[3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      T y = T(0);
+      T y = T(0), x = T(0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         T r, i;
         bent<DAG>(b, k, p, r, i);
         y = fmx(a.re[p][k], i, y);
         y = fmx(a.im[p][k], r, y);
+        if (tr) {
+          x = fmx(a.re[p][k], r, x);
+          x = fmx(-a.im[p][k], i, x);
+        }
       }
       di[p] = y;
+      dr[p] = x;
     }
+    if (tr) *tr = dr[0] + dr[1] + dr[2];
     Alg r;
     r.c[0] = sym[0];
     r.c[1] = asym[0];
@@ -336,6 +347,8 @@ template <typename T> struct Su3 {
   }
   static GL_HD Alg proj_mul(const Link& a, const Link& b) { return proj_prod<false>(a, b); }
   static GL_HD Alg proj_mul_dag(const Link& a, const Link& b) { return proj_prod<true>(a, b); }
+  // proj(a b^dag) and Re Tr(a b^dag) together
+  static GL_HD Alg proj_retr_mul_dag(const Link& a, const Link& b, T& tr) { return proj_prod<true>(a, b, &tr); }
   // hermitian matrix X = sum_a x^a lambda^a / 2, scaled by s
   static GL_HD Link herm(const Alg& x, T s) {
     const T is3 = T(0.57735026918962576451);

@@ -166,22 +166,26 @@ template <typename A> __device__ __forceinline__ A pull_alg(const A& v, int a) {
 // backward plaquettes in the -x direction are the neighbour lane's forward ones carried
 // over by one link: U_{i,-x}(x) = W^dag U_{x,i}(x - e_x) W, W = U_x(x - e_x), and
 // P(W^dag M W) = W^dag P(M) W.
-// The forward plaquettes at x, for the observables: projections and real traces of
-// U_{x,y}, U_{x,z}, U_{y,z}.
-#ifndef GL_PLAQ_ORDER
-#define GL_PLAQ_ORDER 1
-#endif
+// The forward plaquettes at x, for the observables: a hook object receives, for plane K
+// (0 = (x, y), 1 = (x, z), 2 = (y, z)), the projection and real trace of U_{x,y}, U_{x,z}
+// or U_{y,z}, with the force term that is complete at that point (f_x for K = 1, f_y
+// for K = 2; see the group order below).  PlaqObs keeps them for later use.
 template <typename G> struct PlaqObs {
   typename G::Alg p[3];
   typename G::Real tr[3];
+  template <int K>
+  __device__ __forceinline__ void plane(const typename G::Alg& pk, typename G::Real t, const typename G::Alg&) {
+    p[K] = pk;
+    tr[K] = t;
+  }
 };
 
 // own(l, d) sets l = U_d(x) (kept in registers or fetched again).  With OBS the forward
-// plaquettes are also reported in *po.
-template <typename G, bool XS, bool OBS = false, typename F, typename OwnF>
+// plaquettes are also handed to po.
+template <typename G, bool XS, bool OBS = false, typename F, typename OwnF, typename Obs = PlaqObs<G>>
 __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own, const Geom& g, Site x,
                                                  const double* inv_a2, typename G::Alg (&f)[3],
-                                                 PlaqObs<G>* po = nullptr) {
+                                                 Obs* po = nullptr) {
   using L = typename G::Link;
   using Ag = typename G::Alg;
   using R = typename G::Real;
@@ -215,13 +219,11 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     fetch(B, 0, idx(g, xpy));                                 // U_0(x+y)
     A = xs(O1, x, 1, +1);                                     // U_1(x+x)
     const L M2 = G::mul_dag(G::mul(O0, A), B);
-    const Ag p = G::proj_mul_dag(M2, O1);
-    if constexpr (OBS) {
-      po->p[0] = p;
-      po->tr[0] = G::retr_mul_dag(M2, O1);
-    }
+    R tr = R(0);
+    const Ag p = OBS ? G::proj_retr_mul_dag(M2, O1, tr) : G::proj_mul_dag(M2, O1);
     acc(f[0], p, w1);
     acc(f[1], p, -w0);
+    if constexpr (OBS) po->template plane<0>(p, tr, f[0]);
     staple_fence<OBS>();
     if constexpr (XS) {
       // U_{1,-0}(x) = W^dag U_{0,1}(x-x) W with W = U_0(x-x): transport the neighbour
@@ -243,13 +245,11 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     fetch(B, 0, idx(g, xpz));                                 // U_0(x+z)
     A = xs(O2, x, 2, +1);                                     // U_2(x+x)
     const L M2 = G::mul_dag(G::mul(O0, A), B);
-    const Ag p = G::proj_mul_dag(M2, O2);
-    if constexpr (OBS) {
-      po->p[1] = p;
-      po->tr[1] = G::retr_mul_dag(M2, O2);
-    }
+    R tr = R(0);
+    const Ag p = OBS ? G::proj_retr_mul_dag(M2, O2, tr) : G::proj_mul_dag(M2, O2);
     acc(f[0], p, w2);
     acc(f[2], p, -w0);
+    if constexpr (OBS) po->template plane<1>(p, tr, f[0]);   // f_x complete
     staple_fence<OBS>();
     if constexpr (XS) {
       acc(f[2], G::transport(pull_link(O0, xn.am), pull_alg(p, xn.am)), w0);
@@ -269,13 +269,11 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
     fetch(A, 2, idx(g, xpy));                                 // U_2(x+y)
     fetch(B, 1, idx(g, xpz));                                 // U_1(x+z)
     const L M2 = G::mul_dag(G::mul(O1, A), B);
-    const Ag p = G::proj_mul_dag(M2, O2);
-    if constexpr (OBS) {
-      po->p[2] = p;
-      po->tr[2] = G::retr_mul_dag(M2, O2);
-    }
+    R tr = R(0);
+    const Ag p = OBS ? G::proj_retr_mul_dag(M2, O2, tr) : G::proj_mul_dag(M2, O2);
     acc(f[1], p, w2);
     acc(f[2], p, -w1);
+    if constexpr (OBS) po->template plane<2>(p, tr, f[1]);   // f_y complete
     staple_fence<OBS>();
   };
   auto b_my = [&]() {
@@ -310,20 +308,14 @@ __device__ __forceinline__ void plaquette_forces(const F& fetch, const OwnF& own
   };
   // Order of the plaquette groups (the force sums in this order).  The -z group first:
   // its links of layer z - 1 are then loaded while the work-groups of that layer load
-  // them as their own, so they are still in the L2.
-  if constexpr (GL_PLAQ_ORDER == 1) {
-    b_mz();
-    b_xy();
-    b_xz();
-    b_yz();
-    b_my();
-  } else {
-    b_xy();
-    b_xz();
-    b_yz();
-    b_my();
-    b_mz();
-  }
+  // them as their own, so they are still in the L2.  The -y group before the forward
+  // (x, z) and (y, z) groups: f_x is then complete once the (x, z) plaquette is formed and
+  // f_y once the (y, z) one is, so an observer consumes each projection at once.
+  b_mz();
+  b_xy();
+  b_my();
+  b_xz();
+  b_yz();
 }
 
 }  // namespace gl

@@ -36,11 +36,41 @@ template <typename R> __device__ __forceinline__ Q2<double> to_double(const Q2<R
 
 // Observables gathered by an observing step (FP64): the E and B parts of T^{mu nu} at the
 // integer time of the state the step starts from (E averaged over the two half steps,
-// B from the forward plaquettes), the worst link unitarity and a non-finite flag.
-template <typename G> struct ObsAcc {
-  double EL2 = 0.0, ET2 = 0.0, sl = 0.0, uv = 0.0;
+// B from the forward plaquettes), the worst link unitarity and a non-finite flag.  The
+// plaquette sums hand it each forward plaquette (plane<K>); the S_L terms are formed
+// there, with E_i(t + dt/2) computed as the link update computes it, so that no
+// projection stays live until the link update.
+template <typename G, typename T> struct ObsAcc {
+  double EL2 = 0.0, ET2 = 0.0, BL2 = 0.0, BT2 = 0.0, sl = 0.0, uv = 0.0;
   bool bad = false;
-  PlaqObs<G> pl;
+  const T* E;
+  uint32_t s;
+  int64_t Vp;
+  StepConst c;
+  double inv_a2[3];
+  // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) (U_{z,x} = U_{x,z}^dag has the same trace);
+  // S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x) + Ebar_y^a P(U_yz)^a / (a_y a_z))
+  template <int K>
+  __device__ __forceinline__ void plane(const typename G::Alg& p, typename G::Real tr, const typename G::Alg& fi) {
+    const double nc = (double)G::NC;
+    if constexpr (K == 0) {
+      BL2 = 4.0 * inv_a2[0] * inv_a2[1] * (nc - (double)tr);
+    } else {
+      constexpr int i = K - 1;
+      BT2 += 4.0 * inv_a2[i] * inv_a2[2] * (nc - (double)tr);
+      typename G::Alg eo;
+      load_alg_own(eo, E, i, s, Vp);
+      const double ai = c.a[i];
+      const T kf = (T)(-c.dt / ai);
+      double d = 0.0;
+#pragma unroll
+      for (int k = 0; k < G::NG; ++k) {
+        const T en = fmx(kf, fi.c[k], eo.c[k]);
+        d += 0.5 * ((double)eo.c[k] + (double)en) * (double)p.c[k];
+      }
+      sl += d / (c.a[2] * ai);
+    }
+  }
 };
 
 // Update of link (x, i) from the force term f_i of plaquette_forces (F_i = -f_i / a_i);
@@ -49,7 +79,7 @@ template <typename G, typename T, bool HOP, bool OBS = false>
 __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const typename G::Alg& fi,
                                             T* __restrict__ Unew, T* __restrict__ E, T* __restrict__ rhoA,
                                             T* __restrict__ rhoB, const Geom& g, const StepConst& c, Site x,
-                                            uint32_t s, int i, bool reunit, ObsAcc<G>* oa = nullptr) {
+                                            uint32_t s, int i, bool reunit, ObsAcc<G, T>* oa = nullptr) {
   using L = typename G::Link;
   using A = typename G::Alg;
   constexpr int NG = G::NG;
@@ -80,18 +110,11 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
   }
   store_alg(e, E, i, s, Vp);
   if constexpr (OBS) {
-    // E^2 averaged over the half steps; S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x)
-    //                                             + Ebar_y^a P(U_yz)^a / (a_y a_z))
+    // E^2 averaged over the half steps
     const double e2 = 0.5 * (norm2(eo) + norm2(e));
     if (i == 2) oa->EL2 = e2; else oa->ET2 += e2;
-    double d = 0.0;
 #pragma unroll
-    for (int k = 0; k < NG; ++k) {
-      const double pk = i == 0 ? oa->pl.p[1].c[k] : oa->pl.p[2].c[k];
-      d += 0.5 * ((double)eo.c[k] + (double)e.c[k]) * pk;
-      oa->bad |= !isfinite((double)e.c[k]);
-    }
-    if (i < 2) oa->sl += d / (c.a[2] * ai);
+    for (int k = 0; k < NG; ++k) oa->bad |= !isfinite((double)e.c[k]);
     const double uv = (double)G::unit_violation(Ui);
     oa->bad |= !isfinite(uv);
     oa->uv = fmax(oa->uv, uv);
@@ -112,12 +135,12 @@ __device__ __forceinline__ void update_site(const T* __restrict__ U, T* __restri
                                             T* __restrict__ rhoA, T* __restrict__ rhoB, const Geom& g,
                                             const StepConst& c, const double* inv_a2, Site x, uint32_t s,
                                             bool reunit, typename Vec16<T>::type* slot, uint32_t TB,
-                                            ObsAcc<G>* oa = nullptr) {
+                                            ObsAcc<G, T>* oa = nullptr) {
   using L = typename G::Link;
   const GlobalLinks<T> fetch{U, g.Vp};
   const OwnLinks<G, T, OWN> own(fetch, s, slot, threadIdx.x, TB);
   typename G::Alg f[3];
-  if constexpr (OBS) plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &oa->pl);
+  if constexpr (OBS) plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, oa);
   else plaquette_forces<G, XS>(fetch, own, g, x, inv_a2, f);
 #pragma unroll 1
   for (int i = 0; i < 3; ++i) {
@@ -164,15 +187,16 @@ __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __rest
   if constexpr (!OBS) {
     update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
   } else {
-    ObsAcc<G> oa;
+    ObsAcc<G, T> oa;
+    oa.E = E;
+    oa.s = s;
+    oa.Vp = g.Vp;
+    oa.c = c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) oa.inv_a2[k] = inv_a2[k];
     update_site<G, T, HOP, XS, OwnMode<G, T>::value, true>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot,
                                                            LF_BS, &oa);
-    // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) from the forward plaquettes (U_{z,x} = U_{x,z}^dag)
-    const double nc = (double)G::NC;
-    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - oa.pl.tr[0]);
-    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - oa.pl.tr[2]);
-    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - oa.pl.tr[1]);
-    const double BL2 = bxy, BT2 = byz + bzx;
+    const double BL2 = oa.BL2, BT2 = oa.BT2;
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
