@@ -34,6 +34,9 @@ template <typename R> __device__ __forceinline__ Q2<double> to_double(const Q2<R
   return r;
 }
 
+// Work-group size of the step kernel.
+constexpr int LF_BS = 256;
+
 // Observables gathered by an observing step (FP64): the E and B parts of T^{mu nu} at the
 // integer time of the state the step starts from (E averaged over the two half steps,
 // B from the forward plaquettes), the worst link unitarity and a non-finite flag.  The
@@ -41,23 +44,24 @@ template <typename R> __device__ __forceinline__ Q2<double> to_double(const Q2<R
 // there, with E_i(t + dt/2) computed as the link update computes it, so that no
 // projection stays live until the link update.
 template <typename G, typename T> struct ObsAcc {
-  double EL2 = 0.0, ET2 = 0.0, BL2 = 0.0, BT2 = 0.0, sl = 0.0, uv = 0.0;
+  double EL2 = 0.0, ET2 = 0.0, sl = 0.0, uv = 0.0;
   bool bad = false;
   const T* E;
   uint32_t s;
   int64_t Vp;
   StepConst c;
   double inv_a2[3];
+  double* trs;
   // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) (U_{z,x} = U_{x,z}^dag has the same trace);
   // S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x) + Ebar_y^a P(U_yz)^a / (a_y a_z))
+  // The real traces of the forward plaquettes are parked in the work-group's LDS (trs[K][t])
+  // until the end of the step: carried in registers they would hold the step at one wave
+  // per SIMD.
   template <int K>
   __device__ __forceinline__ void plane(const typename G::Alg& p, typename G::Real tr, const typename G::Alg& fi) {
-    const double nc = (double)G::NC;
-    if constexpr (K == 0) {
-      BL2 = 4.0 * inv_a2[0] * inv_a2[1] * (nc - (double)tr);
-    } else {
+    trs[K * LF_BS + threadIdx.x] = (double)tr;
+    if constexpr (K > 0) {
       constexpr int i = K - 1;
-      BT2 += 4.0 * inv_a2[i] * inv_a2[2] * (nc - (double)tr);
       typename G::Alg eo;
       load_alg_own(eo, E, i, s, Vp);
       const double ai = c.a[i];
@@ -171,11 +175,11 @@ template <typename G, typename T, int TB> struct OwnLds {
 #define GL_LF_WAVES 1
 #endif
 // One thread per site, the three directions in turn.
-constexpr int LF_BS = 256;
 // OBS: also gather the observables of the state the step starts from into the partial
 // sums of this work-group (full work-groups only: every thread reaches the reduction).
+// The observing variant is held to two waves per SIMD (its traces live in LDS, below).
 template <typename G, typename T, bool HOP, bool XS, bool OBS = false>
-__global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
+__global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
                                                                  T* __restrict__ E, T* __restrict__ rhoA,
                                                                  T* __restrict__ rhoB, Geom g, StepConst c,
                                                                  ColMap m, double* __restrict__ partial = nullptr) {
@@ -187,7 +191,9 @@ __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __rest
   if constexpr (!OBS) {
     update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
   } else {
+    __shared__ double trs[3 * LF_BS];
     ObsAcc<G, T> oa;
+    oa.trs = trs;
     oa.E = E;
     oa.s = s;
     oa.Vp = g.Vp;
@@ -196,7 +202,12 @@ __global__ void __launch_bounds__(LF_BS, GL_LF_WAVES) k_leapfrog(const T* __rest
     for (int k = 0; k < 3; ++k) oa.inv_a2[k] = inv_a2[k];
     update_site<G, T, HOP, XS, OwnMode<G, T>::value, true>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot,
                                                            LF_BS, &oa);
-    const double BL2 = oa.BL2, BT2 = oa.BT2;
+    // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) (U_{z,x} = U_{x,z}^dag has the same trace); each
+    // thread reads back only its own trace slots
+    const double nc = (double)G::NC;
+    const double BL2 = 4.0 * inv_a2[0] * inv_a2[1] * (nc - trs[threadIdx.x]);
+    double BT2 = 4.0 * inv_a2[0] * inv_a2[2] * (nc - trs[LF_BS + threadIdx.x]);
+    BT2 += 4.0 * inv_a2[1] * inv_a2[2] * (nc - trs[2 * LF_BS + threadIdx.x]);
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
