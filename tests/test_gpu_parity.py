@@ -361,14 +361,16 @@ def test_rest_frame_against_oracle():
     assert np.all(np.abs(got[1]) < 1.0)
 
 
+@pytest.mark.parametrize("n", [5, 6])
 @pytest.mark.parametrize("nc,nz,nt,fp", [(3, 4, 64, 64), (2, 4, 64, 64), (3, 6, 8, 64), (3, 4, 64, 32)])
-def test_step_observe_equals_step_then_observe(nc, nz, nt, fp):
+def test_step_observe_equals_step_then_observe(nc, nz, nt, fp, n):
     """glasma_step_observe(n) against glasma_step(n - 1), glasma_observe, glasma_step(1):
     the same observables (the FP64 nt = 64 cases take the observing step: Gauss pass plus
-    energy slots inside the step kernel) and the same final state."""
+    energy slots inside the step kernel) and the same final state; the observing step is a
+    step without a hop for n = 5 and one with a hop for n = 6 (hops on odd step indices)."""
     pkg = lattice_or_skip()
     import torch
-    say(f"case: step_observe su{nc} {nz}x{nt}x{nt} fp{fp}")
+    say(f"case: step_observe su{nc} {nz}x{nt}x{nt} fp{fp} n={n}")
     dims = (nz, nt, nt)
     ng = nc * nc - 1
     p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=0.5)
@@ -381,7 +383,7 @@ def test_step_observe_equals_step_then_observe(nc, nz, nt, fp):
     a.init_state(*comp, step0=0)
     b.init_state(*comp, step0=0)
     oa, ob = a.obs_buffer(), b.obs_buffer()
-    n = 5
+    assert lattice.is_hop_step(n - 1, p) == (n == 6)
     a.step_observe(n, oa)
     b.step(n - 1)
     b.observe(ob)
