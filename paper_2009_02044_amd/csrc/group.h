@@ -267,18 +267,6 @@ template <typename T> struct Su3 {
     return r;
   }
   static GL_HD T retr(const Link& m) { return m.re[0][0] + m.re[1][1] + m.re[2][2]; }
-  // Re Tr(a b^dag) = sum_ik Re(a_ik conj(b_ik))
-  static GL_HD T retr_mul_dag(const Link& a, const Link& b) {
-    T s = T(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        s = fmx(a.re[i][k], b.re[i][k], s);
-        s = fmx(a.im[i][k], b.im[i][k], s);
-      }
-    return s;
-  }
   // proj(M) of a product M = a b or a b^dag without forming M: each off-diagonal
   // component is one fused chain over the two entries it combines, and only the
   // imaginary diagonal of M is formed (its real part drops out).

@@ -5,9 +5,9 @@
 namespace gl {
 
 // Scheduling fence between plaquette groups: limits how many links the compiler keeps in
-// flight at once.  Off for the plain step (no gain at its two waves per SIMD); on where ON
-// is set, for the observing step, whose extra state leaves it at one wave per SIMD, where
-// the fence shortens it by about an eighth.
+// flight at once.  Off for the plain step (no gain there); on where ON is set, for the
+// observing step, whose extra state keeps it at the edge of its register budget and which
+// the fence shortens.
 #ifndef GL_STAPLE_FENCE
 #define GL_STAPLE_FENCE 0
 #endif

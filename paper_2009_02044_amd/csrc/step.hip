@@ -52,11 +52,10 @@ template <typename G, typename T> struct ObsAcc {
   StepConst c;
   double inv_a2[3];
   double* trs;
-  // B^2 = 4/(a_i a_j)^2 Re Tr(1 - U_ij) (U_{z,x} = U_{x,z}^dag has the same trace);
-  // S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x) + Ebar_y^a P(U_yz)^a / (a_y a_z))
-  // The real traces of the forward plaquettes are parked in the work-group's LDS (trs[K][t])
-  // until the end of the step: carried in registers they would hold the step at one wave
-  // per SIMD.
+  // S_L = sum_a (Ebar_x^a P(U_xz)^a / (a_z a_x) + Ebar_y^a P(U_yz)^a / (a_y a_z)).  The real
+  // traces of the forward plaquettes (for B^2) are parked in the work-group's LDS,
+  // trs[K LF_BS + t], until the end of the step: carried in registers they would hold the
+  // step at one wave per SIMD.
   template <int K>
   __device__ __forceinline__ void plane(const typename G::Alg& p, typename G::Real tr, const typename G::Alg& fi) {
     trs[K * LF_BS + threadIdx.x] = (double)tr;
@@ -174,8 +173,7 @@ template <typename G, typename T, int TB> struct OwnLds {
 #ifndef GL_LF_WAVES
 #define GL_LF_WAVES 1
 #endif
-// One thread per site, the three directions in turn.
-// OBS: also gather the observables of the state the step starts from into the partial
+// One thread per site, the three directions in turn.  OBS: also gather the observables of the state the step starts from into the partial
 // sums of this work-group (full work-groups only: every thread reaches the reduction).
 // The observing variant is held to two waves per SIMD (its traces live in LDS, below).
 template <typename G, typename T, bool HOP, bool XS, bool OBS = false>
