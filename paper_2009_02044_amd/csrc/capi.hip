@@ -391,7 +391,8 @@ static int semi_step(glasma_ctx* c, const StepConst& sc) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
       T* t = in; in = out; out = t;
       c->last_iters = it + 1;
-      if (!(h[0] == h[0]) || !(h[1] == h[1])) return fail(c, GLASMA_E_NONFINITE, "non-finite field in the semi-implicit solve");
+      if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+        return fail(c, GLASMA_E_NONFINITE, "non-finite field in the semi-implicit solve");
       if (h[0] <= c->p.tol * (h[1] > 0 ? h[1] : 1e-300)) { ok = true; break; }
     }
     if (!ok) return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");

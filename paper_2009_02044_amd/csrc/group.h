@@ -421,11 +421,14 @@ template <typename T> struct Su3 {
     c0 = fmx(-q.d[1], n1, c0);
     c0 = fmx(-q.d[2], n0, c0);
     c0 = fmx(T(2), fmx(acr, q.r[1], aci * q.i[1]), c0);
-    // scaling: k halvings bring the spectral radius bound below 1/2
+    // scaling: k halvings bring the spectral radius bound below 1/2.  The count is capped
+    // at what the largest finite value needs (r2 < 2^1024 in double, 2^128 in float), so an
+    // infinite input ends the loop too (its result is non-finite, and reported as such).
     T r2 = T(4) / T(3) * c1;       // bound on the squared spectral radius
     int k = 0;
     T sc = T(1);
-    while (r2 > T(0.25)) { r2 *= T(0.25); sc *= T(0.5); ++k; }
+    constexpr int KMAX = sizeof(T) == 8 ? 600 : 80;
+    while (r2 > T(0.25) && k < KMAX) { r2 *= T(0.25); sc *= T(0.5); ++k; }
     const T c0k = c0 * sc * sc * sc, c1k = c1 * sc * sc;
     // series of exp(i Q_k), Q_k^n = a + b Q_k + c Q_k^2
     constexpr int NT = sizeof(T) == 8 ? 14 : 8;

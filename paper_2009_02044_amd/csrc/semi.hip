@@ -277,7 +277,8 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
 }
 
 // One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
-// Et <- E'; conv[0] = max |E' - Et_old|, conv[1] = max |E'| (component-wise).
+// Et <- E'; conv[0] = max |E' - Et_old| (+inf if E' is not finite), conv[1] = max |E'|
+// (component-wise).
 template <typename G, typename T, bool HOP, int d>
 __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
                                                const T* __restrict__ E, const T* __restrict__ F2,
@@ -305,11 +306,15 @@ __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T
 #pragma unroll
       for (int k = 0; k < G::NG; ++k) e.c[k] += j.c[k];
     }
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < G::NG; ++k) {
       dmax = fmax(dmax, fabs((double)e.c[k] - (double)eo.c[k]));
       emax = fmax(emax, fabs((double)e.c[k]));
+      bad |= !isfinite((double)e.c[k]);
     }
+    // fmax drops a NaN operand: a non-finite field is reported as an infinite update
+    if (bad) dmax = INFINITY;
     // under-relaxed update of the iterate: eo + omega (E' - eo)
     const typename G::Real om = (typename G::Real)omega;
 #pragma unroll

@@ -141,3 +141,23 @@ def test_device_exp_derivative_transpose_matches_expm_frechet(nc):
             xi = -1j * D @ W.conj().T
             ref[b] = np.sum(Lm * su.to_components(xi))
         assert np.abs(got - ref).max() <= 1e-13 * max(1.0, c), (c, amp, got, ref)
+
+
+@pytest.mark.timeout(60)
+@pytest.mark.parametrize("nc", [2, 3])
+@pytest.mark.parametrize("fp", [64, 32])
+def test_device_exp_ends_on_non_finite_input(nc, fp):
+    """The SU(3) exponential halves its argument until its spectral bound is below 1/2; the
+    number of halvings is capped at what the largest finite value needs, so an infinite or
+    NaN argument gives a non-finite matrix instead of an endless loop (the same source runs on
+    the device, where that loop would hang the step kernel)."""
+    from paper_2009_02044_amd import host_group_op
+    ng = nc * nc - 1
+    x = np.zeros((3, 1 + ng))
+    x[:, 0] = 1.0
+    x[0, 1] = np.inf
+    x[1, 1] = np.nan
+    x[2, 1] = 0.5                          # a finite row next to them is unaffected
+    out = host_group_op(nc, fp, 0, x, 4 if nc == 2 else 18)
+    assert not np.isfinite(out[0]).all() and not np.isfinite(out[1]).all()
+    assert np.isfinite(out[2]).all()
