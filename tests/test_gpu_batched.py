@@ -93,3 +93,34 @@ def test_autotune_reports_candidates():
     say("autotune", rep["chosen"])
     o = b.events[0].observables()
     assert o["gauss_rel"] < 1e-4 and o["unitarity"] < 1e-5
+
+
+def test_graph_replays_match_direct_launches():
+    """The captured chunk replayed several times, with the program's own eager work and
+    synchronisations between the replays (observables of every event, a torch reduction),
+    against a batch advanced by direct launches: bitwise equal after every replay (the same
+    kernels; the step counter lives in device memory, so each replay advances it).  Ten steps
+    with reunitarisation every 8 put a reunitarising step inside a replay."""
+    pkg = lattice_or_skip()
+    import torch
+    evs = _events(3)
+    g = pkg.Batch(3, SHAPES, fp=32, reunit_every=8)
+    d = pkg.Batch(3, SHAPES, fp=32, reunit_every=8)
+    for bb in (g, d):
+        bb.set_tiling(128, 0)
+        for (w, rho), lat in zip(evs, bb.events):
+            _init(lat, w, rho)
+    say("case: graph replays against direct launches")
+    for rep in range(5):
+        g.run(2, graph_chunk=2)
+        d.run(2, graph_chunk=0)
+        for lat in g.events:
+            o = lat.observables()
+            assert o["unitarity"] < 1e-5
+        torch.cuda.synchronize()
+        assert torch.ones(1 << 20, device="cuda").sum().item() == float(1 << 20)
+        for e, (a, b) in enumerate(zip(g.events, d.events)):
+            sa, sb = a.get_state(), b.get_state()
+            assert sa["step"] == sb["step"] == 2 * (rep + 1)
+            for k in ("U", "E", "rhoA", "rhoB"):
+                assert np.array_equal(sa[k], sb[k]), (rep, e, k)
