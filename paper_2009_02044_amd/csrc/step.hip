@@ -242,19 +242,26 @@ void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g,
 
 // The observing step: the leapfrog step that also writes the energy slots of the
 // observables of the state it starts from (FP64; nt a multiple of 64, so the column map
-// has only full work-groups and every row lies in a wavefront).
+// has only full work-groups).  x neighbours come from adjacent lanes when a row lies in a
+// wavefront (nt = 64), else from memory, as in the plain step.
 template <typename G, typename T>
 void launch_leapfrog_observe(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
                              double* partial, hipStream_t st) {
   const int bs = LF_BS;
   const ColMap m = col_map(g, bs);
   const unsigned nbc = col_map_blocks(g, m);
-  if (c.hop)
-    hipLaunchKernelGGL((k_leapfrog<G, T, true, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g,
-                       c, m, partial);
-  else
-    hipLaunchKernelGGL((k_leapfrog<G, T, false, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g,
-                       c, m, partial);
+  const bool xs = rows_in_wavefronts(g.nt);
+  if (c.hop) {
+    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, true, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA,
+                               rhoB, g, c, m, partial);
+    else hipLaunchKernelGGL((k_leapfrog<G, T, true, false, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA,
+                            rhoB, g, c, m, partial);
+  } else {
+    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, false, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA,
+                               rhoB, g, c, m, partial);
+    else hipLaunchKernelGGL((k_leapfrog<G, T, false, false, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA,
+                            rhoB, g, c, m, partial);
+  }
 }
 template void launch_leapfrog_observe<Su3<double>, double>(const double*, double*, double*, double*, double*,
                                                           const Geom&, const StepConst&, double*, hipStream_t);
