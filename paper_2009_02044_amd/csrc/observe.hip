@@ -30,8 +30,39 @@ size_t observe_partial_doubles(const Geom& g) {
 }
 
 
+// Plaquette observer of this pass: the S_L terms are formed where the (x, z) and (y, z)
+// plaquettes are (f_x and f_y are complete there, see plaquette_forces), with
+// E(t + dt/2) = E(t - dt/2) - dt f_i / a_i (E(t - dt/2) itself for the semi-implicit scheme);
+// the real traces (for B^2) are parked in LDS, trs[K OBS_BS + t], until the end.  Carrying
+// the projections and traces in registers held the pass at one wave per SIMD.
+template <typename G, typename T> struct PassObs {
+  const T* E;
+  uint32_t s;
+  int64_t Vp;
+  StepConst c;
+  double* trs;
+  double sl = 0.0;
+  template <int K>
+  __device__ __forceinline__ void plane(const typename G::Alg& p, typename G::Real tr, const typename G::Alg& fi) {
+    trs[K * OBS_BS + threadIdx.x] = (double)tr;
+    if constexpr (K > 0) {
+      constexpr int i = K - 1;
+      typename G::Alg eo;
+      load_alg(eo, E, i, s, Vp);
+      const double ai = c.a[i];
+      double d = 0.0;
+#pragma unroll
+      for (int k = 0; k < G::NG; ++k) {
+        const double en = c.scheme == 1 ? eo.c[k] : eo.c[k] - c.dt / ai * fi.c[k];
+        d += 0.5 * (eo.c[k] + en) * p.c[k];
+      }
+      sl += d / (c.a[2] * ai);
+    }
+  }
+};
+
 template <typename G, typename T, bool XS>
-__global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, const T* __restrict__ E,
+__global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, const T* __restrict__ E,
                                                     const T* __restrict__ rhoA, const T* __restrict__ rhoB,
                                                     Geom g, StepConst c, double* __restrict__ partial) {
   using L = typename G::Link;   // double precision group
@@ -42,6 +73,7 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
   const int nbx = gridDim.x;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
   __shared__ typename Vec16<T>::type slot[3 * OwnSlot<G, T>::NCH * OBS_BS];
+  __shared__ double trs[3 * OBS_BS];
   const GlobalLinks<T> fetch{U, Vp};
   double acc[NQ];
 #pragma unroll
@@ -57,10 +89,14 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     // force terms of the E update, and the forward plaquettes, in double precision
     const OwnLinks<G, T, GL_OBS_OWN> own(fetch, s, slot, threadIdx.x, OBS_BS);
     A f[3];
-    PlaqObs<G> pl;
-    plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &pl);
+    PassObs<G, T> ob;
+    ob.E = E;
+    ob.s = s;
+    ob.Vp = Vp;
+    ob.c = c;
+    ob.trs = trs;
+    plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &ob);
     double e2[3];
-    A ebar[2];
     bool bad = false;
     // one direction at a time (i is a run-time value: members are selected, not indexed)
 #pragma unroll 1
@@ -90,11 +126,6 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
       e2[0] = i == 0 ? ei : e2[0];
       e2[1] = i == 1 ? ei : e2[1];
       e2[2] = i == 2 ? ei : e2[2];
-      for (int k = 0; k < NG; ++k) {
-        const double b = 0.5 * (eo.c[k] + en.c[k]);
-        ebar[0].c[k] = i == 0 ? b : ebar[0].c[k];
-        ebar[1].c[k] = i == 1 ? b : ebar[1].c[k];
-      }
       double uv = G::unit_violation(Ui);
       bad |= !isfinite(uv);
       acc[7] = fmax(acc[7], uv);
@@ -102,12 +133,10 @@ __global__ void __launch_bounds__(OBS_BS) k_observe(const T* __restrict__ U, con
     // B^2 from the forward plaquettes U_{x,y}, U_{y,z} and U_{z,x} = U_{x,z}^dag (same
     // real trace); F_yz = P(U_{y,z}), F_zx = P(U_{z,x}) = -P(U_{x,z})
     const double nc = (double)G::NC;
-    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - pl.tr[0]);
-    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - pl.tr[2]);
-    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - pl.tr[1]);
-    const double kyz = 1.0 / (c.a[1] * c.a[2]), kzx = 1.0 / (c.a[2] * c.a[0]);
-    double sl = 0.0;
-    for (int k = 0; k < NG; ++k) sl -= -ebar[0].c[k] * pl.p[1].c[k] * kzx - ebar[1].c[k] * pl.p[2].c[k] * kyz;
+    const double bxy = 4.0 * inv_a2[0] * inv_a2[1] * (nc - trs[threadIdx.x]);
+    const double bzx = 4.0 * inv_a2[2] * inv_a2[0] * (nc - trs[OBS_BS + threadIdx.x]);
+    const double byz = 4.0 * inv_a2[1] * inv_a2[2] * (nc - trs[2 * OBS_BS + threadIdx.x]);
+    const double sl = ob.sl;
     const double EL2 = e2[2], ET2 = e2[0] + e2[1], BL2 = bxy, BT2 = byz + bzx;
     acc[0] += 0.5 * (EL2 + ET2 + BL2 + BT2);
     acc[1] += 0.5 * (ET2 + BT2 - EL2 - BL2);
