@@ -420,6 +420,9 @@ int glasma_step(glasma_ctx* c, int32_t n) {
 // running first on that state and the step kernel adding the energy slots.
 static int one_step(glasma_ctx* c, double* d_obs) {
   StepConst sc = step_const(c);
+  // reunitarisation after this step: inside the plain leapfrog step, else a pass after it
+  const bool ru = c->p.reunit_every > 0 && (c->step + 1) % c->p.reunit_every == 0;
+  bool ru_done = false;
   if (c->p.scheme == 1) {
     int rc = semi_step(c, sc);
     if (rc) return rc;
@@ -438,9 +441,10 @@ static int one_step(glasma_ctx* c, double* d_obs) {
   } else {
     dispatch(c, [&]<typename G, typename T>() -> int {
       launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
-                            c->stream);
+                            ru, c->stream);
       return 0;
     });
+    ru_done = ru;
   }
   c->cur ^= 1;
   if (sc.hop) {
@@ -448,7 +452,7 @@ static int one_step(glasma_ctx* c, double* d_obs) {
     c->offB = (c->offB + 1) % c->g.nz;
   }
   c->step += 1;
-  if (c->p.reunit_every > 0 && c->step % c->p.reunit_every == 0) {
+  if (ru && !ru_done) {
     dispatch(c, [&]<typename G, typename T>() -> int {
       launch_reunit<G, T>(cur_U<T>(c), c->g, c->stream);
       return 0;
@@ -1110,8 +1114,8 @@ int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale,
         sc.hop = is_hop(c, sk + m) ? 1 : 0;
         sc.offA = sc.offB = off_at(c, s0, off0, sk + m);
         sc.scheme = 0;
-        launch_leapfrog<G, T>((const T*)x.U, (T*)y.U, (T*)y.E, (T*)y.rA, (T*)y.rB, c->g, sc, c->stream);
-        if (c->p.reunit_every > 0 && (sk + m + 1) % c->p.reunit_every == 0) launch_reunit<G, T>((T*)y.U, c->g, c->stream);
+        const bool ru = c->p.reunit_every > 0 && (sk + m + 1) % c->p.reunit_every == 0;
+        launch_leapfrog<G, T>((const T*)x.U, (T*)y.U, (T*)y.E, (T*)y.rA, (T*)y.rB, c->g, sc, ru, c->stream);
       }
       for (int64_t m = len - 1; m >= 0; --m) {
         const int64_t s = sk + m;

@@ -6,9 +6,10 @@
 
 namespace gl {
 
+// reunit: the step also reunitarises the new links (as launch_reunit would after it)
 template <typename G, typename T>
 void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
-                     hipStream_t st);
+                     bool reunit, hipStream_t st);
 
 // Batched form (step.hip): one descriptor per event, workgroups loop over work items.
 // Buffers are byte offsets into the batch's pool, whose base is a kernel argument (so

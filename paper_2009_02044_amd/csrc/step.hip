@@ -176,7 +176,8 @@ template <typename G, typename T, int TB> struct OwnLds {
 // One thread per site, the three directions in turn.  OBS: also gather the observables of the state the step starts from into the partial
 // sums of this work-group (full work-groups only: every thread reaches the reduction).
 // The observing variant is held to two waves per SIMD (its traces live in LDS, below).
-template <typename G, typename T, bool HOP, bool XS, bool OBS = false>
+// RU: the step also reunitarises the new links (in double arithmetic, before the store).
+template <typename G, typename T, bool HOP, bool XS, bool OBS = false, bool RU = false>
 __global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const T* __restrict__ U, T* __restrict__ Unew,
                                                                  T* __restrict__ E, T* __restrict__ rhoA,
                                                                  T* __restrict__ rhoB, Geom g, StepConst c,
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const
   if (!col_map_site(g, m, blockIdx.x, threadIdx.x, LF_BS, x, s)) return;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
   if constexpr (!OBS) {
-    update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, false, slot, LF_BS);
+    update_site<G, T, HOP, XS, OwnMode<G, T>::value>(U, Unew, E, rhoA, rhoB, g, c, inv_a2, x, s, RU, slot, LF_BS);
   } else {
     __shared__ double trs[3 * LF_BS];
     ObsAcc<G, T> oa;
@@ -225,18 +226,19 @@ __global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const
 
 template <typename G, typename T>
 void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
-                     hipStream_t st) {
+                     bool reunit, hipStream_t st) {
   const int bs = LF_BS;
   const ColMap m = col_map(g, bs);
-  const unsigned nbc = col_map_blocks(g, m);
+  const dim3 grid(col_map_blocks(g, m));
   // rows inside wavefronts: x neighbours from other lanes
   const bool xs = rows_in_wavefronts(g.nt);
-  if (c.hop) {
-    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, true, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-    else hipLaunchKernelGGL((k_leapfrog<G, T, true, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+  auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, grid, dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m, nullptr); };
+  if (!reunit) {
+    if (c.hop) xs ? go(k_leapfrog<G, T, true, true>) : go(k_leapfrog<G, T, true, false>);
+    else xs ? go(k_leapfrog<G, T, false, true>) : go(k_leapfrog<G, T, false, false>);
   } else {
-    if (xs) hipLaunchKernelGGL((k_leapfrog<G, T, false, true>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
-    else hipLaunchKernelGGL((k_leapfrog<G, T, false, false>), dim3(nbc), dim3(bs), 0, st, U, Unew, E, rhoA, rhoB, g, c, m);
+    if (c.hop) xs ? go(k_leapfrog<G, T, true, true, false, true>) : go(k_leapfrog<G, T, true, false, false, true>);
+    else xs ? go(k_leapfrog<G, T, false, true, false, true>) : go(k_leapfrog<G, T, false, false, false, true>);
   }
 }
 
@@ -339,9 +341,9 @@ template void launch_batch_step<Su3<double>, double>(char*, const EventDesc*, co
 template void launch_batch_step<Su2<float>, float>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
 template void launch_batch_step<Su3<float>, float>(char*, const EventDesc*, const uint32_t*, const BatchConst&, const int64_t*, int, int, hipStream_t);
 
-template void launch_leapfrog<Su2<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);
-template void launch_leapfrog<Su3<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, hipStream_t);
-template void launch_leapfrog<Su2<float>, float>(const float*, float*, float*, float*, float*, const Geom&, const StepConst&, hipStream_t);
-template void launch_leapfrog<Su3<float>, float>(const float*, float*, float*, float*, float*, const Geom&, const StepConst&, hipStream_t);
+template void launch_leapfrog<Su2<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, bool, hipStream_t);
+template void launch_leapfrog<Su3<double>, double>(const double*, double*, double*, double*, double*, const Geom&, const StepConst&, bool, hipStream_t);
+template void launch_leapfrog<Su2<float>, float>(const float*, float*, float*, float*, float*, const Geom&, const StepConst&, bool, hipStream_t);
+template void launch_leapfrog<Su3<float>, float>(const float*, float*, float*, float*, float*, const Geom&, const StepConst&, bool, hipStream_t);
 
 }  // namespace gl
