@@ -5,20 +5,23 @@ SU(3), a_T = 4 a_L, dt = a_L/2, two MV nuclei (mu = 0.5, sigma = 8 a_L, m = 0.2,
 Lambda = 10/a_T), initial state built on the GPU.  One step = one leapfrog update of
 every link and E field with the CPIC charge hop on every second step; observables
 (T^{mu nu} slices, Gauss residual, energy) are reduced every 16 steps inside the
-timed region (by the observing step: glasma_step_observe).  Inputs are resident in HBM before timing starts.
+timed region (by the observing step, glasma_step_observe, on every 16th step of the timed
+run).  Inputs are resident in HBM before timing starts.
 
-The JSON line reports site-updates/s of the FP64 single-event form (value), the
-roofline of its dominant kernel (the fused leapfrog step, timed with HIP events on
-the library's stream), the FP32 single-event form, the FP32 batched form (64 events
-of N_z in {128,256,384} x N_T in {32,48,64}, 512 steps, HIP-graph replay, autotuned
-tiling, event-averaged T^{mu nu}(z)), the semi-implicit scheme on the headline
+The printed JSON line (scalars only, a few KB) reports site-updates/s of the FP64
+single-event form (value), the roofline of its dominant kernel (the fused leapfrog step,
+timed with HIP events on the library's stream), the FP32 single-event form, the FP32
+batched form (64 events of N_z in {128,256,384} x N_T in {32,48,64}, 512 steps, HIP-graph
+replay, autotuned tiling, event-averaged T^{mu nu}(z) on the device, and the relative error
+of its observables against an FP64 run of the same events), the semi-implicit scheme on the headline
 lattice, the differentiation form (gradient of the central-slab energy after 256 steps of
 a 256 x 32 x 32 lattice, FP32 forward with checkpoints every 32 steps, FP64 reverse pass),
 the local rest frame at the collision point after the collision (eps_loc from diagonalising
 T^{mu nu}), nuclei of 8 colour sheets along the beam axis against the single sheet (GPU
 initial conditions, energy between the receding nuclei), the approach of thin nuclei to the
-boost-invariant Glasma at mid-rapidity, optionally the FP32-vs-FP64 precision study on the 2048 x 192 x 192 lattice, and
-the FP64 CPU oracle timed on the host.
+boost-invariant Glasma at mid-rapidity, optionally the FP32-vs-FP64 precision study on the
+2048 x 192 x 192 lattice, and the FP64 CPU oracle timed on the host.  Per-layer arrays and
+tables go to the --detail file.
 """
 import argparse
 import hashlib
@@ -86,32 +89,45 @@ def run_plain(w, fp, steps, warmup, obs_every=16, scheme=0, tol=1e-12):
     t0 = time.perf_counter()
     done = 0
     iters = []
+    n_obs = 0
     while done < steps:
         n = min(obs_every, steps - done)
-        if scheme == 1:
-            for _ in range(n):
-                lat.step(1)
+        if n == obs_every:
+            # the last step of the chunk also reduces the observables of the state it starts
+            # from (glasma_step_observe): observables every obs_every steps of the timed run
+            if scheme == 1:
+                lat.step(n - 1)
+                lat.step_observe(1, obs)
                 iters.append(lat.last_iterations)
-            lat.observe(obs)
+            else:
+                lat.step_observe(n, obs)
+            n_obs += 1
         else:
-            # the last step of each chunk also reduces the observables (glasma_step_observe)
-            lat.step_observe(n, obs)
+            lat.step(n)
+        if scheme == 1:
+            iters.append(lat.last_iterations)
         done += n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+    out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "observing_steps": n_obs,
            "site_updates_per_s": w.sites * steps / wall}
     if scheme == 0:
-        # the dominant kernel alone, HIP events on the library's stream
+        # the dominant kernel alone (plain steps, no observables), HIP events recorded on the
+        # library's stream; an even number of steps so that hop and no-hop steps are balanced
         st = lat.stream
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nk = max(2, steps + (steps & 1))
         ev0.record(st)
-        lat.step(steps)
+        lat.step(nk)
         ev1.record(st)
         torch.cuda.synchronize()
-        out["kernel_ms"] = ev0.elapsed_time(ev1) / steps
+        out["kernel_ms"] = ev0.elapsed_time(ev1) / nk
+        out["kernel_steps"] = nk
     else:
-        out["iterations_mean"] = float(np.mean(iters))
+        # per-step iteration counts of the timed run (last_iterations after each chunk)
+        out["iterations_mean"] = float(np.mean(iters)) if iters else 0.0
+    if n_obs == 0:
+        lat.observe(obs)
     o = pkg.Lattice.unpack_obs(obs, w.nz)
     out.update({"gauss_rel": o["gauss_rel"], "energy": o["energy"], "unitarity": o["unitarity"]})
     return out
@@ -258,22 +274,29 @@ def run_rhic_profile(events, m_values=(0.2, 0.4, 0.8), T_fm=2.6):
     return out
 
 
-def run_batched(steps, warmup, graph_chunk=16):
-    """64 events, SU(3) FP32: autotuned tiling, then the timed run; returns throughput and
-    the event-averaged T^{mu nu}(z) per N_z class (transverse means averaged over events)."""
+def run_batched(steps, warmup, graph_chunk=16, n_grid=64, compare_fp64=True):
+    """64 events, SU(3) FP32: autotuned tiling, then the timed run (HIP-graph replay); the
+    event-averaged T^{mu nu}(z) on the device (glasma_batch_observe: per N_z class and on a
+    common z / N_z grid of n_grid bins).  With compare_fp64 the same 64 events (same initial
+    conditions) run the same number of steps in FP64 and the FP32 observables are compared
+    with them: the error of the FP32 form at the step count it is timed at."""
     import torch
     import synth
     import paper_2009_02044_amd as pkg
     evs = synth.batched_events()
     shapes = [(w.nz, w.nt) for w in evs]
-    b = pkg.Batch(3, shapes, a_T=4.0, a_L=1.0, dt=0.5, fp=32, reunit_every=8)
 
-    def init():
-        for w, lat in zip(evs, b.events):
-            rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
-            lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
-        b.stream.synchronize()
+    def make(fp):
+        b = pkg.Batch(3, shapes, a_T=4.0, a_L=1.0, dt=0.5, fp=fp, reunit_every=8 if fp == 32 else 0)
 
+        def init():
+            for w, lat in zip(evs, b.events):
+                rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
+                lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma, zA=w.zA, zB=w.zB)
+            b.stream.synchronize()
+        return b, init
+
+    b, init = make(32)
     init()
     tune = b.autotune(steps=2)
     init()
@@ -283,17 +306,51 @@ def run_batched(steps, warmup, graph_chunk=16):
     b.run(steps, graph_chunk=graph_chunk)
     b.stream.synchronize()
     wall = time.perf_counter() - t0
-    sums, counts, gauss, unit = {}, {}, 0.0, 0.0
-    for w, lat in zip(evs, b.events):
-        o = lat.observables()
-        sums[w.nz] = sums.get(w.nz, 0) + o["tmunu_z"]
-        counts[w.nz] = counts.get(w.nz, 0) + 1
-        gauss = max(gauss, o["gauss_rel"])
-        unit = max(unit, o["unitarity"])
-    avg = {str(k): (sums[k] / counts[k]).tolist() for k in sorted(sums)}
-    return {"site_updates_per_s": b.sites * steps / wall, "ms_per_step": 1e3 * wall / steps,
-            "sites": b.sites, "events": len(evs), "steps": steps, "tiling": tune["chosen"],
-            "gauss_rel_max": gauss, "unitarity_max": unit, "tmunu_z_event_avg_by_nz": avg}
+    r32 = b.observe(n_grid, per_event=True)
+    b.stream.synchronize()
+    pe32 = r32["per_event"].cpu().numpy()
+    out = {"site_updates_per_s": b.sites * steps / wall, "ms_per_step": 1e3 * wall / steps, "sites": b.sites, "events": len(evs),
+           "steps": warmup + steps, "timed_steps": steps, "tiling": tune["chosen"],
+           "classes": b.classes(), "n_grid": n_grid,
+           "tmunu_z_event_avg_grid": r32["grid"].cpu().numpy().tolist(),
+           "tmunu_z_event_avg_by_nz": {str(k): v.cpu().numpy().tolist() for k, v in r32["class"].items()}}
+    nz_list = [w.nz for w in evs]
+    g32 = [o["gauss_rel"] for o in (b.events[e].observables() for e in range(len(evs)))]
+    out["gauss_rel_max"] = float(max(g32))
+    del b, r32
+    torch.cuda.empty_cache()
+    if not compare_fp64:
+        return out
+    b64, init64 = make(64)
+    init64()
+    b64.run(warmup + steps, graph_chunk=graph_chunk)
+    r64 = b64.observe(n_grid, per_event=True)
+    b64.stream.synchronize()
+    pe64 = r64["per_event"].cpu().numpy()
+    # per-event relative errors of the slices (max over z / max |FP64 slice|) and totals
+    rows, off = [], 0
+    for e, nz in enumerate(nz_list):
+        a = pe32[off:off + 4 * nz].reshape(4, nz)
+        c = pe64[off:off + 4 * nz].reshape(4, nz)
+        row = {}
+        for q, name in enumerate(("eps", "pL", "pT")):
+            row[name + "_slices"] = float(np.abs(a[q] - c[q]).max() / np.abs(c[q]).max())
+            row[name + "_total"] = float(abs(a[q].sum() - c[q].sum()) / abs(c[q].sum()))
+        hs = pe32[off + 4 * nz], pe64[off + 4 * nz]
+        row["H"] = float(abs(hs[0] - hs[1]) / abs(hs[1]))
+        rows.append(row)
+        off += 4 * nz + 8
+    keys = list(rows[0])
+    err = {k: {"max": float(max(r[k] for r in rows)), "median": float(np.median([r[k] for r in rows]))} for k in keys}
+    grid32 = np.array(out["tmunu_z_event_avg_grid"])
+    grid64 = r64["grid"].cpu().numpy()
+    for q, name in enumerate(("eps", "pL", "pT")):
+        err["event_avg_grid_" + name] = float(np.abs(grid32[q] - grid64[q]).max() / np.abs(grid64[q]).max())
+    out["fp32_vs_fp64_same_events"] = err
+    out["fp32_vs_fp64_per_event"] = rows
+    del b64, r64
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_adjoint(w, steps, every, fp=32):
@@ -395,7 +452,23 @@ def cpu_baseline(w, budget_s=20.0):
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
             "sample": f"{n} leapfrog steps of a {nz}x{ws.nt}x{ws.nt} slab of the headline "
                       f"lattice (SU({ws.nc}), FP64 NumPy)",
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def scalars(d, keep):
+    """The entries of d named in keep whose values are numbers or short strings."""
+    return {k: d[k] for k in keep if k in d and isinstance(d[k], (int, float, str, type(None)))}
 
 
 def main():
@@ -406,6 +479,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched-fp64", action="store_true",
+                    help="skip the FP64 run of the batched events (the at-fixed-error comparison)")
     ap.add_argument("--no-semi", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=512)
     ap.add_argument("--semi-steps", type=int, default=8)
@@ -413,6 +488,8 @@ def main():
     ap.add_argument("--no-rest-frame", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
     ap.add_argument("--no-bi-limit", action="store_true")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full results (per-layer arrays, tables); the printed line holds scalars")
     ap.add_argument("--rhic-profile", type=int, default=0,
                     help="also run the RHIC 200 GeV rapidity-profile study with this many events per m")
     ap.add_argument("--precision-study", action="store_true",
@@ -430,29 +507,43 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
+        print("bench.py runs on one GPU: this build has no multi-GPU path (the z-slab sharding "
+              "is a design only); run it with --gpus 1", file=sys.stderr)
+        print(json.dumps({"error": "one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     import synth
     w = synth.PLAIN_SU3
     r64 = run_plain(w, 64, args.steps, args.warmup)
     print(f"[bench] fp64 {w.name}: {r64['site_updates_per_s']:.3e} site-updates/s, "
           f"kernel {r64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
-    forms = {}
+    forms, detail = {}, {"fp64_plain": r64}
     if not args.no_fp32:
         r32 = run_plain(w, 32, args.steps, args.warmup)
         b32 = algorithmic_bytes_per_site_update(3, 32, w.dt / w.a_L)
         forms["fp32_plain"] = {
             "site_updates_per_s": r32["site_updates_per_s"], "kernel_ms": r32["kernel_ms"],
+            "kernel_site_updates_per_s": w.sites / (r32["kernel_ms"] * 1e-3),
             "hbm_frac": b32 * w.sites / (r32["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "gauss_rel": r32["gauss_rel"], "unitarity": r32["unitarity"]}
+        detail["fp32_plain"] = r32
         print(f"[bench] fp32 {w.name}: {r32['site_updates_per_s']:.3e} site-updates/s",
               file=sys.stderr, flush=True)
     if not args.no_batched:
-        rb = run_batched(args.batched_steps, 8)
+        rb = run_batched(args.batched_steps, 8, compare_fp64=not args.no_batched_fp64)
         bb = algorithmic_bytes_per_site_update(3, 32, 0.5)
         rb["hbm_frac"] = bb * rb["site_updates_per_s"] / 1e9 / HBM_PEAK_GBS
         rb["vs_fp64_plain"] = rb["site_updates_per_s"] / r64["site_updates_per_s"]
-        forms["fp32_batched"] = rb
+        detail["fp32_batched"] = rb
+        fb = scalars(rb, ("site_updates_per_s", "ms_per_step", "hbm_frac", "vs_fp64_plain", "sites", "events",
+                          "steps", "gauss_rel_max"))
+        fb["tiling"] = rb["tiling"]
+        if "fp32_vs_fp64_same_events" in rb:
+            e = rb["fp32_vs_fp64_same_events"]
+            fb["rel_err_vs_fp64_max_over_events"] = {k: round(v["max"], 9) for k, v in e.items()
+                                                     if isinstance(v, dict)}
+            fb["rel_err_event_avg"] = {k[len("event_avg_grid_"):]: round(v, 9) for k, v in e.items()
+                                       if k.startswith("event_avg_grid_")}
+        forms["fp32_batched"] = fb
         print(f"[bench] fp32 batched 64 events: {rb['site_updates_per_s']:.3e} site-updates/s "
               f"({rb['vs_fp64_plain']:.2f}x fp64 plain)", file=sys.stderr, flush=True)
     if not args.no_semi:
@@ -460,42 +551,51 @@ def main():
             ws = synth.Workload(w.name, nc=3, nz=w.nz, nt=w.nt, dt=dt, mu=w.mu, sigma=w.sigma,
                                 uv_cut=w.uv_cut, seed=w.seed)
             rs = run_plain(ws, 64, args.semi_steps, 1, obs_every=4, scheme=1, tol=1e-12)
-            forms[f"semi_implicit_fp64_dt{dt}"] = {
-                "site_updates_per_s": rs["site_updates_per_s"], "ms_per_step": rs["ms_per_step"],
-                "iterations_mean": rs["iterations_mean"], "tol": 1e-12, "gauss_rel": rs["gauss_rel"]}
+            key = f"semi_implicit_fp64_dt{dt}"
+            forms[key] = scalars(rs, ("site_updates_per_s", "ms_per_step", "iterations_mean", "gauss_rel"))
+            forms[key]["tol"] = 1e-12
+            detail[key] = rs
             print(f"[bench] semi-implicit dt={dt}: {rs['site_updates_per_s']:.3e} site-updates/s, "
                   f"{rs['iterations_mean']:.1f} iterations", file=sys.stderr, flush=True)
     if not args.no_adjoint:
         wa = synth.ADJOINT_SU3
         ra = run_adjoint(wa, wa.steps, 32)
-        forms["adjoint_fp32_fwd_fp64_rev"] = ra
+        forms["adjoint_fp32_fwd_fp64_rev"] = scalars(ra, ("site_updates_per_s", "forward_s", "backward_s",
+                                                          "backward_over_forward", "steps", "ckpt_every"))
+        detail["adjoint"] = ra
         print(f"[bench] adjoint {wa.name}: forward {ra['forward_s']:.3f} s, backward {ra['backward_s']:.3f} s",
               file=sys.stderr, flush=True)
     if not args.no_rest_frame:
-        forms["rest_frame_collision_point"] = run_rest_frame(w)
-        r = forms["rest_frame_collision_point"]["rows"][-1]
+        detail["rest_frame_collision_point"] = rf = run_rest_frame(w)
+        r = rf["rows"][-1]
+        forms["rest_frame_collision_point"] = {k: r[k] for k in ("tau", "eps_loc_tau", "2pT_over_eps_loc",
+                                                                  "pL_over_eps_loc")}
         print(f"[bench] rest frame at z_c: tau {r['tau']:.0f}, eps_loc tau {r['eps_loc_tau']:.3e}, "
               f"2pT/eps_loc {r['2pT_over_eps_loc']:.3f}, pL/eps_loc {r['pL_over_eps_loc']:.3f}",
               file=sys.stderr, flush=True)
     if not args.no_sheets:
-        forms["colour_sheets"] = r = run_sheets(w)
+        detail["colour_sheets"] = r = run_sheets(w)
         one, many, thin = r["ns1"], r["ns%d" % r["ns"]], r["ns1_thin"]
         a, b, c = one["rows"][-1], many["rows"][-1], thin["rows"][-1]
+        forms["colour_sheets"] = {"ns": r["ns"], "init_ms": many["init_ms"],
+                                  "glasma_energy_ratio_vs_one_sheet": b["glasma_energy"] / a["glasma_energy"]}
         print(f"[bench] {r['ns']} colour sheets: init {many['init_ms']:.1f} ms (1 sheet {one['init_ms']:.1f} ms); "
               f"at tau {a['tau']:.0f} glasma energy {b['glasma_energy']:.4g} vs {a['glasma_energy']:.4g} (1 sheet) "
               f"and {c['glasma_energy']:.4g} (1 sheet, sigma/{r['ns']})", file=sys.stderr, flush=True)
     if not args.no_bi_limit:
-        forms["boost_invariant_limit"] = r = run_bi_limit()
+        detail["boost_invariant_limit"] = r = run_bi_limit()
+        forms["boost_invariant_limit"] = {f"sigma{row['sigma']:g}": round(row["pT_over_eps0_max"], 4)
+                                          for row in r["rows"] if row["scheme"] == "semi-implicit"}
         for row in r["rows"]:
             if row["scheme"] == "semi-implicit":
                 print(f"[bench] boost-invariant limit, semi-implicit, sigma {row['sigma']:g}: "
                       f"max p_T/eps_0 {row['pT_over_eps0_max']:.3f}, min p_L/eps {row['pL_over_eps_min']:+.3f}",
                       file=sys.stderr, flush=True)
     if args.rhic_profile > 0:
-        forms["rhic200_rapidity_profile"] = run_rhic_profile(args.rhic_profile)
+        detail["rhic200_rapidity_profile"] = run_rhic_profile(args.rhic_profile)
     if args.precision_study:
         wp = synth.PRECISION_SU3
-        forms["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)
+        detail["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)
     bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
     launch_bytes = bpsu * w.sites
     achieved = launch_bytes / (r64["kernel_ms"] * 1e-3) / 1e9
@@ -504,7 +604,7 @@ def main():
         cpu = cpu_baseline(w)
         print(f"[bench] cpu oracle: {cpu['value']:.3e} site-updates/s", file=sys.stderr, flush=True)
     line = {
-        "metric": "site-updates/s (SU(3) FP64 leapfrog + CPIC, single event)",
+        "metric": "site-updates/s + HBM GB/s fraction; FP32-batched vs FP64-plain at fixed error",
         "value": r64["site_updates_per_s"],
         "unit": "site-updates/s",
         "n_gpus": 1,
@@ -516,16 +616,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (MV charges, seeded)",
-        "config": {"workload": w.name, "nc": 3, "lattice": [w.nz, w.nt, w.nt], "a_T": w.a_T,
-                   "dt": w.dt, "scheme": "leapfrog", "obs_every": 16},
+        "config": {"workload": w.name, "form": "plain SU(3) FP64 leapfrog + CPIC, single event", "nc": 3,
+                   "lattice": [w.nz, w.nt, w.nt], "a_T": w.a_T, "dt": w.dt, "scheme": "leapfrog",
+                   "obs_every": 16, "observing_steps_timed": r64["observing_steps"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
                      "kernel": "k_leapfrog<Su3<double>,double,hop,xs=true>", "kernel_ms": r64["kernel_ms"],
-                     "bytes_per_site_update": bpsu, "bytes_per_launch": launch_bytes},
+                     "kernel_site_updates_per_s": w.sites / (r64["kernel_ms"] * 1e-3),
+                     "bytes_per_site_update": bpsu,
+                     "bytes_row": "SU(3) FP64, links stored by 2 rows (12 reals): 2(288 + 192) + 128 x dt/a_L",
+                     "bytes_per_launch": launch_bytes},
         "checks": {"gauss_rel": r64["gauss_rel"], "unitarity": r64["unitarity"]},
         "forms": forms,
         "cpu_baseline": cpu,
+        "detail_file": args.detail,
     }
+    if args.detail:
+        d = os.path.dirname(args.detail)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.detail, "w") as fh:
+            json.dump({"line": line, "detail": detail}, fh)
     print(json.dumps(line), flush=True)
 
 

@@ -175,8 +175,11 @@ int glasma_bi_fields(const glasma_params* p, const glasma_mv* mv, int32_t ns, co
  * reunit_every steps when set).  Asynchronous for the leapfrog.  The semi-implicit step
  * iterates its fixed point (under-relaxed) until max|dE| <= tol max|E|, from a start
  * extrapolated from the previous step when the context made that step; after a state
- * upload it starts from E, so a resumed run agrees with an uninterrupted one to tol.
- * GLASMA_E_NOCONV after max_iter iterations, GLASMA_E_NONFINITE on a non-finite field. */
+ * upload it starts from E, so a resumed run agrees with an uninterrupted one to tol.  Its
+ * iterations are enqueued in batches that test convergence on the device; the host waits
+ * once per batch (usually once per step).  GLASMA_E_NOCONV after max_iter iterations,
+ * GLASMA_E_NONFINITE on a non-finite field; either leaves the state (links, E, charges,
+ * step counter) as it was before the failed step, so the context stays consistent. */
 int glasma_step(glasma_ctx* ctx, int32_t n);
 
 /* Current j (device, 3 * n_g * V reals of the context's precision, in the plain host
@@ -188,8 +191,15 @@ int glasma_deposit_current(glasma_ctx* ctx, void* j_out);
 
 /* Observables at the current integer time into device memory d_out (double,
  * 4 * nz + GLASMA_OBS_NSCALARS): eps, p_L, p_T, S_L slices (Sec. 4, <T^{mu nu}> and
- * eq. pT_eL) computed in double precision, then the scalars listed above.  Does not
- * change the state.  Asynchronous. */
+ * eq. pT_eL) computed in double precision, then the scalars listed above.  Electric terms
+ * average the two half steps, E^2 = (|E(t - dt/2)|^2 + |E(t + dt/2)|^2)/2 and
+ * Ebar = (E(t - dt/2) + E(t + dt/2))/2 in S_L, for both schemes: the leapfrog's E(t + dt/2)
+ * is computed here; the semi-implicit scheme's comes from solving the next step (that solve
+ * is discarded; the call then waits for it and fails like glasma_step).  Magnetic terms
+ * are the plain plaquettes at t for both schemes, so for the semi-implicit scheme H is the
+ * Wilson-action energy, not the conserved energy of its modified action.  The Gauss slots
+ * hold the standard residual at (U(t), E(t - dt/2), rho(t - dt/2)).  Does not change the
+ * state.  Asynchronous for the leapfrog. */
 int glasma_observe(glasma_ctx* ctx, double* d_out);
 
 /* n >= 1 steps, writing to d_out (device, as glasma_observe) the observables of the state
@@ -197,9 +207,10 @@ int glasma_observe(glasma_ctx* ctx, double* d_out);
  * glasma_step(1), up to rounding.  For the FP64 leapfrog with nt a multiple of 64 the last
  * step computes them on the way (a Gauss-residual pass over the state before it, the
  * energy slots inside the step kernel, which has the forces and plaquettes at hand), at a
- * fraction of a separate glasma_observe; otherwise it runs exactly that sequence.  The
- * non-finite slot then counts detections (a site may count twice).  Asynchronous; errors
- * as glasma_step. */
+ * fraction of a separate glasma_observe; the non-finite slot then counts detections (a
+ * site may count twice).  For the semi-implicit scheme the observables pass runs between
+ * the last step's converged solve and its commit (one solve, not two).  Otherwise it runs
+ * exactly that sequence.  Asynchronous for the leapfrog; errors as glasma_step. */
 int glasma_step_observe(glasma_ctx* ctx, int32_t n, double* d_out);
 
 /* Local rest frame of every layer (Sec. 4: the local energy density from diagonalising
@@ -315,6 +326,28 @@ int glasma_batch_event(glasma_batch* b, int32_t e, glasma_ctx** ctx);
 /* Advance every event by `steps` steps; graph_chunk > 0 captures that many steps in a
  * HIP graph (kept for later calls with the same chunk and tiling) and replays it. */
 int glasma_batch_run(glasma_batch* b, int32_t steps, int32_t graph_chunk);
+
+/* N_z classes of the batch's events (distinct N_z, ascending): n_classes, and, for each
+ * class k, nz_of_class[k] and events_of_class[k] (either array may be NULL; each needs room
+ * for n_events entries at most).  Host values. */
+int glasma_batch_classes(const glasma_batch* b, int32_t* n_classes, int32_t* nz_of_class, int32_t* events_of_class);
+
+/* Event average of T^{mu nu}(z) at the current integer time (Sec. 2 eq. ev: the average
+ * over the MV ensemble, estimated by the mean over the batch's independent events; Sec. 4
+ * <T^{mu nu}>).  Every event's observables (as glasma_observe, into the pool), then, on the
+ * device, the eps, p_L, p_T, S_L slices averaged
+ *   class_avg: per N_z class (order of glasma_batch_classes), the mean over that class's
+ *              events of the [4][N_z] slices, the classes' blocks one after another;
+ *   grid_avg:  [4][n_grid], the mean over all events on a common grid of relative position
+ *              z / N_z: bin b of an event is the mean of its layers z with
+ *              floor(z n_grid / N_z) = b (1 <= n_grid <= the smallest N_z, so no bin is
+ *              empty);
+ *   per_event: (may be NULL) every event's observables buffer, 4 N_z + GLASMA_OBS_NSCALARS
+ *              doubles each, events in order.
+ * All output pointers are caller-owned device double arrays.  Asynchronous on the batch's
+ * stream; GLASMA_E_ARG for a bad n_grid or NULL outputs, GLASMA_E_STATE if an event has
+ * no state. */
+int glasma_batch_observe(glasma_batch* b, int32_t n_grid, double* class_avg, double* grid_avg, double* per_event);
 
 /* Work-item tiling: sites per item (64, 128 or 256 threads per workgroup) and the
  * number of persistent workgroups (0: one workgroup per item). */

@@ -13,8 +13,7 @@ import os
 import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# GLASMA_LIB selects another build of the same library (e.g. a tuning variant).
-LIB_PATH = os.environ.get("GLASMA_LIB") or os.path.join(HERE, "libglasma.so")
+LIB_PATH = os.path.join(HERE, "libglasma.so")
 
 GLASMA_OK = 0
 ERRORS = {-1: "GLASMA_E_ARG", -2: "GLASMA_E_HIP", -3: "GLASMA_E_NONFINITE",
@@ -87,6 +86,8 @@ def _load():
         "glasma_batch_event": ([P, I32, C.POINTER(P)], C.c_int),
         "glasma_batch_run": ([P, I32, I32], C.c_int),
         "glasma_batch_set_tiling": ([P, I32, I32], C.c_int),
+        "glasma_batch_classes": ([P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)], C.c_int),
+        "glasma_batch_observe": ([P, I32, V, V, V], C.c_int),
         "glasma_batch_autotune": ([P, I32, C.c_char_p, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sig.items():

@@ -105,6 +105,8 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct SemiRegion {
   size_t up, ut, et, f2, j, ep, conv, end;  // byte offsets
 };
+// convergence slots (2 doubles per iteration) of one batch of enqueued iterations
+constexpr int SEMI_SLOTS = 64;
 static size_t general_bytes(const glasma_params* p) {
   Geom g = geom_of(p);
   int ng = p->nc * p->nc - 1;
@@ -126,7 +128,7 @@ static SemiRegion semi_region(const glasma_params* p) {
   s.j = s.f2 + align256(3 * (size_t)ng * g.Vp * e);
   s.ep = s.j + align256((size_t)ng * g.Vp * e);
   s.conv = s.ep + align256(3 * (size_t)ng * g.Vp * e);
-  s.end = s.conv + 256;
+  s.end = s.conv + SEMI_SLOTS * 2 * sizeof(double);
   return s;
 }
 static size_t work_bytes(const glasma_params* p) {
@@ -359,50 +361,98 @@ int glasma_bi_fields(const glasma_params* p, const glasma_mv* mv, int32_t ns, co
   return GLASMA_OK;
 }
 
-// One semi-implicit step: U(t - dt), f1(U(t), U(t - dt)) and the hop once, then fixed-point
-// iterations on E(t + dt/2) until max|dE| <= tol max|E|; the new links end in next_U.
-static int semi_step(glasma_ctx* c, const StepConst& sc) {
+// Semi-implicit solve of the step from the current state: the current of the hop (the
+// charges stay where they are), U(t - dt) and f1(U(t), U(t - dt)) once, then fixed-point
+// iterations on E(t + dt/2) until max|dE| <= tol max|E|.  Iterations are enqueued in batches
+// (the first as long as the last step needed, plus one); each writes its convergence slot
+// and does nothing once the slot before it has converged, so the host reads the slots once
+// per batch.  On success the converged E(t + dt/2) is in the work region's trial E and
+// *links points at the new links (next_U or the trial-link buffer).  Nothing of the state
+// (links, E, charges, step) is changed, so an error leaves the state as it was.
+static int semi_solve(glasma_ctx* c, const StepConst& sc, void** links) {
   const SemiRegion r = semi_region(&c->p);
   char* w = (char*)c->b.work;
   double* conv = (double*)(w + r.conv);
-  double h[2];
   return dispatch(c, [&]<typename G, typename T>() -> int {
     T* Uc = cur_U<T>(c);
-    T* Un = next_U<T>(c);
     T* Up = (T*)(w + r.up);
-    T* Ub = (T*)(w + r.ut);
     T* Et = (T*)(w + r.et);
     T* F2 = (T*)(w + r.f2);
     T* J = (T*)(w + r.j);
     T* Ep = (T*)(w + r.ep);
-    // the hop first: its current enters the starting guess
-    if (sc.hop) launch_semi_hop<G, T>(Uc, (T*)c->b.rhoA, (T*)c->b.rhoB, J, c->g, sc, c->stream);
-    launch_semi_begin<G, T>(Uc, (T*)c->b.E, c->semi_prev ? Ep : nullptr, sc.hop ? J : nullptr, Up, Un, Et, c->g,
+    // the current first: it enters the starting guess
+    if (sc.hop) launch_semi_hop<G, T>(Uc, (T*)c->b.rhoA, (T*)c->b.rhoB, J, false, c->g, sc, c->stream);
+    T* buf[2] = {next_U<T>(c), (T*)(w + r.ut)};   // iteration k reads buf[k & 1], writes buf[(k + 1) & 1]
+    launch_semi_begin<G, T>(Uc, (T*)c->b.E, c->semi_prev ? Ep : nullptr, sc.hop ? J : nullptr, Up, buf[0], Et, c->g,
                             sc, c->stream);
     launch_semi_f1<G, T>(Uc, Up, F2, c->g, sc, c->stream);
-    T* in = Un;
-    T* out = Ub;
-    bool ok = false;
-    for (int it = 0; it < c->p.max_iter; ++it) {
-      HIPCHK(c, hipMemsetAsync(conv, 0, 2 * sizeof(double), c->stream));
-      launch_semi_iter<G, T>(Uc, in, (T*)c->b.E, F2, J, Et, out, conv, c->g, sc, c->stream);
+    double h[2 * SEMI_SLOTS];
+    int done = 0, at = -1;
+    while (done < c->p.max_iter && at < 0) {
+      int nb = done == 0 ? std::max(c->last_iters + 1, 3) : 4;
+      nb = std::min(std::min(nb, SEMI_SLOTS), c->p.max_iter - done);
+      launch_zero(conv, 2 * nb, c->stream);
+      for (int k = 0; k < nb; ++k) {
+        const int it = done + k;
+        launch_semi_iter<G, T>(Uc, buf[it & 1], (T*)c->b.E, F2, J, Et, buf[(it + 1) & 1], conv + 2 * k,
+                               k ? conv + 2 * (k - 1) : nullptr, c->p.tol, c->g, sc, c->stream);
+      }
       HIPCHK(c, hipGetLastError());
-      HIPCHK(c, hipMemcpyAsync(h, conv, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(h, conv, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
-      T* t = in; in = out; out = t;
-      c->last_iters = it + 1;
-      if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
-        return fail(c, GLASMA_E_NONFINITE, "non-finite field in the semi-implicit solve");
-      if (h[0] <= c->p.tol * (h[1] > 0 ? h[1] : 1e-300)) { ok = true; break; }
+      for (int k = 0; k < nb; ++k) {
+        const double d = h[2 * k], e = h[2 * k + 1];
+        if (!std::isfinite(d) || !std::isfinite(e)) {
+          c->last_iters = done + k + 1;
+          return fail(c, GLASMA_E_NONFINITE, "non-finite field in the semi-implicit solve");
+        }
+        if (d <= c->p.tol * (e > 0 ? e : 1e-300)) { at = done + k; break; }
+      }
+      done += nb;
     }
-    if (!ok) return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");
-    const int64_t nl = 3 * (int64_t)c->rs * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
-    if (in != Un) launch_copy<G, T>(in, Un, nl, c->stream);
-    launch_semi_keep<G, T>((T*)c->b.E, sc.hop ? J : nullptr, Ep, c->g, c->stream);
-    launch_copy<G, T>(Et, (T*)c->b.E, ne, c->stream);
-    c->semi_prev = true;
+    if (at < 0) {
+      c->last_iters = done;
+      return fail(c, GLASMA_E_NOCONV, "semi-implicit iteration reached max_iter");
+    }
+    c->last_iters = at + 1;
+    *links = buf[(at + 1) & 1];
     return GLASMA_OK;
   });
+}
+
+// Accept a converged solve: new links into next_U, the reference of the next step's
+// starting guess, E(t + dt/2) into E, and the hop of the charges (with U(t)).
+static int semi_commit(glasma_ctx* c, const StepConst& sc, void* links) {
+  const SemiRegion r = semi_region(&c->p);
+  char* w = (char*)c->b.work;
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    T* Un = next_U<T>(c);
+    T* J = (T*)(w + r.j);
+    const int64_t nl = 3 * (int64_t)c->rs * c->g.Vp, ne = 3 * (int64_t)c->ng * c->g.Vp;
+    if ((T*)links != Un) launch_copy<G, T>((const T*)links, Un, nl, c->stream);
+    launch_semi_keep<G, T>((T*)c->b.E, sc.hop ? J : nullptr, (T*)(w + r.ep), c->g, c->stream);
+    launch_copy<G, T>((const T*)(w + r.et), (T*)c->b.E, ne, c->stream);
+    if (sc.hop) launch_semi_hop<G, T>(cur_U<T>(c), (T*)c->b.rhoA, (T*)c->b.rhoB, J, true, c->g, sc, c->stream);
+    return 0;
+  });
+  c->semi_prev = true;
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+// Observables of the current state for the semi-implicit scheme, with E(t + dt/2) from the
+// converged solve of the step that follows (its trial E in the work region).
+static int semi_observe_solved(glasma_ctx* c, const StepConst& sc, double* d_obs) {
+  const SemiRegion r = semi_region(&c->p);
+  char* w = (char*)c->b.work;
+  double* partial = (double*)c->b.work;
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, (const T*)(w + r.et), c->g, sc,
+                         partial, d_obs, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
 }
 
 static int advance(glasma_ctx* c, int32_t n);
@@ -415,17 +465,22 @@ int glasma_step(glasma_ctx* c, int32_t n) {
   return advance(c, n);
 }
 
-// One step; with d_obs (the observing step: FP64 leapfrog, nt a multiple of 64) it also
-// writes to d_obs the observables of the state it starts from, the Gauss residual kernel
-// running first on that state and the step kernel adding the energy slots.
+// One step; with d_obs (the observing step: FP64 leapfrog with nt a multiple of 64, or the
+// semi-implicit scheme) it also writes to d_obs the observables of the state it starts from:
+// for the leapfrog the Gauss residual kernel runs first on that state and the step kernel
+// adds the energy slots; for the semi-implicit scheme the observables pass runs between the
+// converged solve and its commit, with E(t + dt/2) from the solve.
 static int one_step(glasma_ctx* c, double* d_obs) {
   StepConst sc = step_const(c);
   // reunitarisation after this step: inside the plain leapfrog step, else a pass after it
   const bool ru = c->p.reunit_every > 0 && (c->step + 1) % c->p.reunit_every == 0;
   bool ru_done = false;
   if (c->p.scheme == 1) {
-    int rc = semi_step(c, sc);
+    void* links = nullptr;
+    int rc = semi_solve(c, sc, &links);
     if (rc) return rc;
+    if (d_obs && (rc = semi_observe_solved(c, sc, d_obs))) return rc;
+    if ((rc = semi_commit(c, sc, links))) return rc;
   } else if (d_obs) {
     double* partial = (double*)c->b.work;
     dispatch(c, [&]<typename G, typename T>() -> int {
@@ -477,7 +532,7 @@ int glasma_step_observe(glasma_ctx* c, int32_t n, double* d_out) {
   c->adj_ok = false;
   int rc = advance(c, n - 1);
   if (rc) return rc;
-  if (c->p.fp == 64 && c->p.scheme == 0 && fused_observe_geometry(c->g)) return one_step(c, d_out);
+  if (c->p.scheme == 1 || (c->p.fp == 64 && fused_observe_geometry(c->g))) return one_step(c, d_out);
   rc = glasma_observe(c, d_out);
   if (rc) return rc;
   return advance(c, 1);
@@ -511,10 +566,19 @@ int glasma_observe(glasma_ctx* c, double* d_out) {
   if (!c || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
   StepConst sc = step_const(c);
+  if (c->p.scheme == 1) {
+    // E(t + dt/2) needs the solve of the next step: solve it, observe, and discard it
+    const int iters = c->last_iters;
+    void* links = nullptr;
+    int rc = semi_solve(c, sc, &links);
+    c->last_iters = iters;
+    if (rc) return rc;
+    return semi_observe_solved(c, sc, d_out);
+  }
   double* partial = (double*)c->b.work;
   dispatch(c, [&]<typename G, typename T>() -> int {
-    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, partial, d_out,
-                         c->stream);
+    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, (const T*)nullptr, c->g, sc, partial,
+                         d_out, c->stream);
     return 0;
   });
   HIPCHK(c, hipGetLastError());
@@ -682,6 +746,12 @@ struct glasma_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   int graph_steps, graph_bs, graph_grid;
+  // event averages: every event's observables buffer, the averaging table, N_z classes
+  double* d_obs;
+  std::vector<int64_t> obs_off;    // doubles from d_obs to each event's buffer
+  BatchObsEvent* d_avg_ev;
+  int* d_cls;                      // [n] class N_z | [n + 1] class offsets | [n] class counts
+  std::vector<int> cls_nz, cls_off, cls_count;
   std::string err;
   std::string tune_report;
 };
@@ -706,49 +776,64 @@ static glasma_params event_params(const glasma_params* common, int32_t nz, int32
 }
 
 // pool layout: per event [U | U_alt | E | rhoA | rhoB | work], then the event table,
-// the item map for the smallest work item (64 sites) and the step counter
+// the item map for the smallest work item (64 sites), the step counter, every event's
+// observables buffer (4 nz + GLASMA_OBS_NSCALARS doubles) and the averaging tables
+struct BatchLayout {
+  std::vector<size_t> ev;          // byte offset of each event's buffers
+  std::vector<int64_t> obs;        // doubles from the observables region to each event's buffer
+  size_t table, items, ctr, obs_region, avg_ev, cls, total;
+};
 static int batch_sizes(const glasma_params* common, int32_t n, const int32_t* nz, const int32_t* nt,
-                       std::vector<size_t>* offs, size_t* table_off, size_t* items_off, size_t* ctr_off,
-                       size_t* total) {
+                       BatchLayout* L) {
   if (!common || n < 1 || !nz || !nt) return fail(nullptr, GLASMA_E_ARG, "bad batch arguments");
   if (common->scheme != 0) return fail(nullptr, GLASMA_E_ARG, "the batched form runs the leapfrog scheme");
   size_t off = 0;
   uint64_t items64 = 0;
+  int64_t nobs = 0;
   for (int32_t e = 0; e < n; ++e) {
     glasma_params q = event_params(common, nz[e], nt[e]);
     size_t b[6];
     int rc = glasma_layout(&q, b);
     if (rc) return rc;
-    if (offs) offs->push_back(off);
+    L->ev.push_back(off);
     for (int k = 0; k < 6; ++k) off += align256(b[k]);
     items64 += (uint64_t)(geom_of(&q).V + 63) / 64;
+    L->obs.push_back(nobs);
+    nobs += 4 * (int64_t)nz[e] + GLASMA_OBS_NSCALARS;
   }
-  *table_off = off;
+  L->table = off;
   off += align256((size_t)n * sizeof(EventDesc));
-  *items_off = off;
+  L->items = off;
   off += align256((size_t)items64 * sizeof(uint32_t));
-  *ctr_off = off;
+  L->ctr = off;
   off += 256;
-  *total = off;
+  L->obs_region = off;
+  off += align256((size_t)nobs * sizeof(double));
+  L->avg_ev = off;
+  off += align256((size_t)n * sizeof(BatchObsEvent));
+  L->cls = off;
+  off += align256((size_t)(3 * n + 1) * sizeof(int));
+  L->total = off;
   return GLASMA_OK;
 }
 
 int glasma_batch_layout(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
                         size_t* pool_bytes) {
-  size_t t, i, c, tot;
-  int rc = batch_sizes(common, n_events, nz, nt, nullptr, &t, &i, &c, &tot);
+  BatchLayout L;
+  int rc = batch_sizes(common, n_events, nz, nt, &L);
   if (rc) return rc;
   if (!pool_bytes) return fail(nullptr, GLASMA_E_ARG, "pool_bytes is NULL");
-  *pool_bytes = tot;
+  *pool_bytes = L.total;
   return GLASMA_OK;
 }
 
 int glasma_batch_create(const glasma_params* common, int32_t n_events, const int32_t* nz, const int32_t* nt,
                         void* pool, void* stream, glasma_batch** out) {
-  std::vector<size_t> offs;
-  size_t toff, ioff, coff, tot;
-  int rc = batch_sizes(common, n_events, nz, nt, &offs, &toff, &ioff, &coff, &tot);
+  BatchLayout L;
+  int rc = batch_sizes(common, n_events, nz, nt, &L);
   if (rc) return rc;
+  const std::vector<size_t>& offs = L.ev;
+  const size_t toff = L.table, ioff = L.items, coff = L.ctr;
   if (!pool || !out) return fail(nullptr, GLASMA_E_ARG, "pool or out is NULL");
   glasma_batch* b = new glasma_batch();
   b->p = *common;
@@ -781,7 +866,75 @@ int glasma_batch_create(const glasma_params* common, int32_t n_events, const int
   b->graph = nullptr;
   b->exec = nullptr;
   b->graph_steps = b->graph_bs = b->graph_grid = 0;
+  // N_z classes (ascending) and the averaging tables
+  b->d_obs = (double*)(b->pool + L.obs_region);
+  b->obs_off = L.obs;
+  b->d_avg_ev = (BatchObsEvent*)(b->pool + L.avg_ev);
+  b->d_cls = (int*)(b->pool + L.cls);
+  std::vector<int> nzs(nz, nz + n_events);
+  std::sort(nzs.begin(), nzs.end());
+  nzs.erase(std::unique(nzs.begin(), nzs.end()), nzs.end());
+  b->cls_nz = nzs;
+  b->cls_count.assign(nzs.size(), 0);
+  std::vector<BatchObsEvent> tab(n_events);
+  for (int32_t e = 0; e < n_events; ++e) {
+    const int k = (int)(std::lower_bound(nzs.begin(), nzs.end(), nz[e]) - nzs.begin());
+    tab[e].off = L.obs[e];
+    tab[e].nz = nz[e];
+    tab[e].cls = k;
+    b->cls_count[k] += 1;
+  }
+  b->cls_off.assign(nzs.size() + 1, 0);
+  for (size_t k = 0; k < nzs.size(); ++k) b->cls_off[k + 1] = b->cls_off[k] + 4 * nzs[k];
+  std::vector<int> ints(3 * (size_t)n_events + 1, 0);
+  for (size_t k = 0; k < nzs.size(); ++k) {
+    ints[k] = nzs[k];
+    ints[n_events + k] = b->cls_off[k];
+    ints[2 * n_events + 1 + k] = b->cls_count[k];
+  }
+  ints[n_events + nzs.size()] = b->cls_off[nzs.size()];
+  hipError_t he = hipMemcpyAsync(b->d_avg_ev, tab.data(), tab.size() * sizeof(BatchObsEvent), hipMemcpyHostToDevice,
+                                 b->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(b->d_cls, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
+  if (he != hipSuccess) {
+    for (auto* x : b->ev) glasma_destroy(x);
+    delete b;
+    return fail(nullptr, GLASMA_E_HIP, std::string("batch tables: ") + hipGetErrorString(he));
+  }
   *out = b;
+  return GLASMA_OK;
+}
+
+int glasma_batch_classes(const glasma_batch* b, int32_t* n_classes, int32_t* nz_of_class, int32_t* events_of_class) {
+  if (!b || !n_classes) return fail(nullptr, GLASMA_E_ARG, "NULL argument");
+  *n_classes = (int32_t)b->cls_nz.size();
+  for (size_t k = 0; k < b->cls_nz.size(); ++k) {
+    if (nz_of_class) nz_of_class[k] = b->cls_nz[k];
+    if (events_of_class) events_of_class[k] = b->cls_count[k];
+  }
+  return GLASMA_OK;
+}
+
+int glasma_batch_observe(glasma_batch* b, int32_t n_grid, double* class_avg, double* grid_avg, double* per_event) {
+  if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
+  if (!class_avg || !grid_avg) return bfail(b, GLASMA_E_ARG, "class_avg and grid_avg must be device pointers");
+  if (n_grid < 1 || n_grid > b->cls_nz.front()) return bfail(b, GLASMA_E_ARG, "need 1 <= n_grid <= the smallest N_z");
+  const int n = (int)b->ev.size();
+  for (int e = 0; e < n; ++e) {
+    glasma_ctx* c = b->ev[e];
+    if (!c->ready) return bfail(b, GLASMA_E_STATE, "an event has no state");
+    int rc = glasma_observe(c, b->d_obs + b->obs_off[e]);
+    if (rc) return bfail(b, rc, std::string("event observables: ") + c->err);
+  }
+  launch_batch_average(b->d_obs, b->d_avg_ev, n, b->d_cls, b->d_cls + n, b->d_cls + 2 * n + 1,
+                       (int)b->cls_nz.size(), b->cls_off.back(), n_grid, class_avg, grid_avg, b->stream);
+  BHIPCHK(b, hipGetLastError());
+  if (per_event)
+    BHIPCHK(b, hipMemcpyAsync(per_event, b->d_obs, (size_t)(b->obs_off.back() + 4 * b->ev.back()->g.nz +
+                                                            GLASMA_OBS_NSCALARS) * sizeof(double),
+                              hipMemcpyDeviceToDevice, b->stream));
   return GLASMA_OK;
 }
 

@@ -38,13 +38,14 @@ void launch_batch_step(char* pool, const EventDesc* ev, const uint32_t* item_eve
 void launch_batch_tick(int64_t* ctr, hipStream_t st);
 
 // Observables at the current integer time, written to `out` (device, double):
-// [0, 4 nz): transverse means eps, p_L, p_T, S_L per layer; then OBS_* scalars.
+// [0, 4 nz): transverse means eps, p_L, p_T, S_L per layer; then OBS_* scalars.  En: E(t + dt/2)
+// from the semi-implicit solve of the next step (null: the leapfrog update, computed here).
 enum {
   OBS_ENERGY = 0, OBS_GAUSS_L2, OBS_RHO_L2, OBS_GAUSS_MAX, OBS_UNITARITY, OBS_NONFINITE,
   OBS_GAUSS_REL, OBS_NSCALARS = 8
 };
 template <typename G, typename T>
-void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
+void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const T* En, const Geom& g,
                     const StepConst& c, double* partial, double* out, hipStream_t st);
 size_t observe_partial_doubles(const Geom& g);
 // Observing step (FP64 leapfrog, nt a multiple of 64): the Gauss residual kernel runs on
@@ -59,6 +60,15 @@ void launch_leapfrog_observe(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const 
                              double* partial, hipStream_t st);
 void launch_observe_finish(const double* partial, int nbx, const Geom& g, const StepConst& c, double* out,
                            hipStream_t st);
+// event averages of a batch's observables (class averages per N_z, common z / N_z grid)
+struct BatchObsEvent {
+  int64_t off;   // doubles from the start of the observables region
+  int nz;
+  int cls;       // index of the event's N_z class
+};
+void launch_batch_average(const double* obs, const BatchObsEvent* ev, int n_events, const int* cls_nz,
+                          const int* cls_off, const int* cls_count, int n_cls, int cls_total, int n_grid,
+                          double* cls_out, double* grid_out, hipStream_t st);
 // local rest frame per layer from the observe slices (2 * nz doubles out)
 void launch_rest_frame(const double* obs, int nz, double* out, hipStream_t st);
 
@@ -77,11 +87,18 @@ void launch_semi_begin(const T* U, const T* E, const T* Ep, const T* J, T* Up, T
                        const StepConst& c, hipStream_t st);
 template <typename G, typename T>
 void launch_semi_keep(const T* E, const T* J, T* Ep, const Geom& g, hipStream_t st);
+// hop of the charges with U(t): commit = false writes only the current a_L (rho_A' - rho_B) into J,
+// commit = true moves the charges (after the solve has converged)
 template <typename G, typename T>
-void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, const Geom& g, const StepConst& c, hipStream_t st);
+void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, bool commit, const Geom& g, const StepConst& c,
+                     hipStream_t st);
+// one fixed-point iteration; conv (2 doubles, zeroed before) receives max|dE|, max|E|; with
+// conv_prev (the slot of the iteration before) already converged to tol it does nothing
 template <typename G, typename T>
 void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
-                      double* conv, const Geom& g, const StepConst& c, hipStream_t st);
+                      double* conv, const double* conv_prev, double tol, const Geom& g, const StepConst& c,
+                      hipStream_t st);
+void launch_zero(double* p, int n, hipStream_t st);
 template <typename G, typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 

@@ -2,7 +2,9 @@
 // the CPIC current of the next step, and FP64 reunitarisation of the links.
 //
 // At integer time t (state U(t), E(t - dt/2), rho(t - dt/2)) every thread recomputes
-// the E update of its site in double precision without applying it, then forms
+// the leapfrog E update of its site in double precision without applying it (or, for the
+// semi-implicit scheme, reads E(t + dt/2) from the converged solve of the step that
+// follows, En), then forms
 //   E_i^2 = (|E_i(t-dt/2)|^2 + |E_i(t+dt/2)|^2)/2,
 //   B_ij^2 = 4/(a_i a_j)^2 Re Tr(1 - U_{i,j}),  F_ij^a = proj(U_{i,j})^a / (a_i a_j),
 //   eps = (E^2 + B^2)/2, p_T = (E_L^2 + B_L^2)/2, p_L = (E_T^2 + B_T^2 - E_L^2 - B_L^2)/2,
@@ -32,11 +34,12 @@ size_t observe_partial_doubles(const Geom& g) {
 
 // Plaquette observer of this pass: the S_L terms are formed where the (x, z) and (y, z)
 // plaquettes are (f_x and f_y are complete there, see plaquette_forces), with
-// E(t + dt/2) = E(t - dt/2) - dt f_i / a_i (E(t - dt/2) itself for the semi-implicit scheme);
+// E(t + dt/2) = E(t - dt/2) - dt f_i / a_i (leapfrog) or read from En (semi-implicit);
 // the real traces (for B^2) are parked in LDS, trs[K OBS_BS + t], until the end.  Carrying
 // the projections and traces in registers held the pass at one wave per SIMD.
 template <typename G, typename T> struct PassObs {
   const T* E;
+  const T* En;
   uint32_t s;
   int64_t Vp;
   StepConst c;
@@ -47,13 +50,14 @@ template <typename G, typename T> struct PassObs {
     trs[K * OBS_BS + threadIdx.x] = (double)tr;
     if constexpr (K > 0) {
       constexpr int i = K - 1;
-      typename G::Alg eo;
+      typename G::Alg eo, enx;
       load_alg(eo, E, i, s, Vp);
+      if (En) load_alg(enx, En, i, s, Vp);
       const double ai = c.a[i];
       double d = 0.0;
 #pragma unroll
       for (int k = 0; k < G::NG; ++k) {
-        const double en = c.scheme == 1 ? eo.c[k] : eo.c[k] - c.dt / ai * fi.c[k];
+        const double en = En ? (double)enx.c[k] : eo.c[k] - c.dt / ai * fi.c[k];
         d += 0.5 * (eo.c[k] + en) * p.c[k];
       }
       sl += d / (c.a[2] * ai);
@@ -64,7 +68,8 @@ template <typename G, typename T> struct PassObs {
 template <typename G, typename T, bool XS>
 __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, const T* __restrict__ E,
                                                     const T* __restrict__ rhoA, const T* __restrict__ rhoB,
-                                                    Geom g, StepConst c, double* __restrict__ partial) {
+                                                    const T* __restrict__ En, Geom g, StepConst c,
+                                                    double* __restrict__ partial) {
   using L = typename G::Link;   // double precision group
   using A = typename G::Alg;
   constexpr int NG = G::NG;
@@ -91,6 +96,7 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
     A f[3];
     PassObs<G, T> ob;
     ob.E = E;
+    ob.En = En;
     ob.s = s;
     ob.Vp = Vp;
     ob.c = c;
@@ -104,17 +110,18 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
       const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
       A eo, en;
       load_alg(eo, E, i, s, Vp);
-      for (int k = 0; k < NG; ++k) {
-        const double fk = i == 0 ? f[0].c[k] : (i == 1 ? f[1].c[k] : f[2].c[k]);
-        en.c[k] = eo.c[k] - c.dt / ai * fk;
+      if (En) {
+        // semi-implicit scheme: E(t + dt/2) of the converged solve (the current included)
+        load_alg(en, En, i, s, Vp);
+      } else {
+        for (int k = 0; k < NG; ++k) {
+          const double fk = i == 0 ? f[0].c[k] : (i == 1 ? f[1].c[k] : f[2].c[k]);
+          en.c[k] = eo.c[k] - c.dt / ai * fk;
+        }
       }
-      // semi-implicit scheme: E(t + dt/2) needs the next implicit solve; its
-      // observables use E(t - dt/2) for both half steps
-      if (c.scheme == 1)
-        for (int k = 0; k < NG; ++k) en.c[k] = eo.c[k];
       L Ui;
       own(Ui, i);
-      if (c.hop && i == 2 && c.scheme == 0) {
+      if (c.hop && i == 2 && !En) {
         A rb, ra;
         load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
         load_alg(ra, rhoA, 0, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), Vp);
@@ -263,15 +270,17 @@ __global__ void __launch_bounds__(256) k_observe_finish(const double* __restrict
 }
 
 template <typename G, typename T>
-void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g,
+void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const T* En, const Geom& g,
                     const StepConst& c, double* partial, double* out, hipStream_t st) {
   using Gd = typename GroupOf<G::NC, double>::type;
   const int nbx = obs_blocks_per_layer(g);
   // blocks start at multiples of 64 sites of a layer: rows lie in wavefronts when nt divides 64
   if (rows_in_wavefronts(g.nt))
-    hipLaunchKernelGGL((k_observe<Gd, T, true>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+    hipLaunchKernelGGL((k_observe<Gd, T, true>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c,
+                       partial);
   else
-    hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, partial);
+    hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c,
+                       partial);
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 
@@ -307,6 +316,46 @@ __global__ void k_rest_frame(const double* __restrict__ obs, int nz, double* __r
 }
 void launch_rest_frame(const double* obs, int nz, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_rest_frame, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, obs, nz, out);
+}
+
+// ---- event averages of the slices over a batch (Sec. 2 eq. ev; Sec. 4) ----------------
+// obs: the events' observables buffers, event e at obs + ev[e].off (4 nz_e slices first).
+// Output element t < cls_total: class averages (class k's [4][nz_k] block at cls_off[k]);
+// after that the common grid [4][n_grid] of relative position z / nz, bin b = floor(z n_grid / nz).
+__global__ void k_batch_average(const double* __restrict__ obs, const BatchObsEvent* __restrict__ ev, int n_events,
+                                const int* __restrict__ cls_nz, const int* __restrict__ cls_off,
+                                const int* __restrict__ cls_count, int n_cls, int cls_total, int n_grid,
+                                double* __restrict__ cls_out, double* __restrict__ grid_out) {
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t < cls_total) {
+    int k = 0;
+    while (k + 1 < n_cls && t >= cls_off[k + 1]) ++k;
+    const int nz = cls_nz[k], r = t - cls_off[k], q = r / nz, z = r % nz;
+    double sum = 0.0;
+    for (int e = 0; e < n_events; ++e)
+      if (ev[e].cls == k) sum += obs[ev[e].off + (int64_t)q * nz + z];
+    cls_out[t] = sum / (double)cls_count[k];
+  } else if (t < cls_total + 4 * n_grid) {
+    const int r = t - cls_total, q = r / n_grid, b = r % n_grid;
+    double sum = 0.0;
+    for (int e = 0; e < n_events; ++e) {
+      const int nz = ev[e].nz;
+      // layers z with floor(z n_grid / nz) = b: z in [ceil(b nz / n_grid), ceil((b + 1) nz / n_grid))
+      const int z0 = (int)(((int64_t)b * nz + n_grid - 1) / n_grid);
+      const int z1 = (int)(((int64_t)(b + 1) * nz + n_grid - 1) / n_grid);
+      double m = 0.0;
+      for (int z = z0; z < z1; ++z) m += obs[ev[e].off + (int64_t)q * nz + z];
+      sum += m / (double)(z1 - z0);
+    }
+    grid_out[r] = sum / (double)n_events;
+  }
+}
+void launch_batch_average(const double* obs, const BatchObsEvent* ev, int n_events, const int* cls_nz,
+                          const int* cls_off, const int* cls_count, int n_cls, int cls_total, int n_grid,
+                          double* cls_out, double* grid_out, hipStream_t st) {
+  const int n = cls_total + 4 * n_grid;
+  hipLaunchKernelGGL(k_batch_average, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, obs, ev, n_events, cls_nz,
+                     cls_off, cls_count, n_cls, cls_total, n_grid, cls_out, grid_out);
 }
 
 // ---- current of the next step (tests) --------------------------------------
@@ -369,7 +418,8 @@ void launch_reunit(T* U, const Geom& g, hipStream_t st) {
 }
 
 #define GL_INST(G, T)                                                                                       \
-  template void launch_observe<G, T>(const T*, const T*, const T*, const T*, const Geom&, const StepConst&, \
+  template void launch_observe<G, T>(const T*, const T*, const T*, const T*, const T*, const Geom&,             \
+                                     const StepConst&,                                                      \
                                      double*, double*, hipStream_t);                                        \
   template void launch_current<G, T>(const T*, const T*, const T*, const Geom&, const StepConst&, T*,      \
                                      hipStream_t);                                                          \

@@ -243,8 +243,10 @@ __global__ void __launch_bounds__(256) k_semi_keep(const T* __restrict__ E, cons
   store_alg(e, Ep, d, s, g.Vp);
 }
 
-// hop of both charge populations with the links U(t) and the current dt j_z = a_L (rho_A' - rho_B)
-template <typename G, typename T>
+// The hop of both charge populations with the links U(t): COMMIT = false writes only the
+// current dt j_z = a_L (rho_A' - rho_B) (the solve needs it; the charges stay where they are
+// until the solve has converged), COMMIT = true moves the charges in place (J unused).
+template <typename G, typename T, bool COMMIT>
 __global__ void __launch_bounds__(256) k_semi_hop(const T* __restrict__ U, T* __restrict__ rhoA,
                                                   T* __restrict__ rhoB, T* __restrict__ J, Geom g, StepConst c) {
   using A = typename G::Alg;
@@ -260,15 +262,24 @@ __global__ void __launch_bounds__(256) k_semi_hop(const T* __restrict__ U, T* __
   A rb, ra;
   load_alg_own(rb, rhoB, 0, sB, Vp);
   load_alg_own(ra, rhoA, 0, sA, Vp);
-  A rbn = G::transport(Uz, rb);
   A ran = G::transport_inv(Uz, ra);
-  store_alg(rbn, rhoB, 0, sB, Vp);
-  store_alg(ran, rhoA, 0, sA, Vp);
-  A jz;
-  const typename G::Real al = (typename G::Real)c.a[2];
+  if constexpr (COMMIT) {
+    store_alg(G::transport(Uz, rb), rhoB, 0, sB, Vp);
+    store_alg(ran, rhoA, 0, sA, Vp);
+  } else {
+    A jz;
+    const typename G::Real al = (typename G::Real)c.a[2];
 #pragma unroll
-  for (int k = 0; k < G::NG; ++k) jz.c[k] = al * (ran.c[k] - rb.c[k]);
-  store_alg(jz, J, 0, s, Vp);
+    for (int k = 0; k < G::NG; ++k) jz.c[k] = al * (ran.c[k] - rb.c[k]);
+    store_alg(jz, J, 0, s, Vp);
+  }
+}
+
+// zero n doubles (the convergence slots of a batch of iterations; a kernel, not a memset,
+// so that the sequence stays capturable)
+__global__ void k_zero(double* __restrict__ p, int n) {
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k < n) p[k] = 0.0;
 }
 
 __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
@@ -276,16 +287,27 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
   atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
 }
 
+// Convergence test of an iteration's slot: max |dE| <= tol max |E| (both 0: converged).
+// A non-finite field leaves +inf in conv[0], which never passes.
+__device__ __forceinline__ bool semi_converged(const double* conv, double tol) {
+  const double e = conv[1];
+  return conv[0] <= tol * (e > 0.0 ? e : 1e-300);
+}
+
 // One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
 // Et <- E'; conv[0] = max |E' - Et_old| (+inf if E' is not finite), conv[1] = max |E'|
-// (component-wise).
+// (component-wise).  When the previous iteration's slot conv_prev already passes the test
+// the iteration does nothing (every thread returns): the host enqueues several iterations
+// at once and reads their slots afterwards.
 template <typename G, typename T, bool HOP, int d>
 __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
                                                const T* __restrict__ E, const T* __restrict__ F2,
                                                const T* __restrict__ J, T* __restrict__ Et,
-                                               T* __restrict__ Ut_out, double* __restrict__ conv, const Geom& g,
+                                               T* __restrict__ Ut_out, double* __restrict__ conv,
+                                               const double* __restrict__ conv_prev, double tol, const Geom& g,
                                                const StepConst& c, double omega) {
   using A = typename G::Alg;
+  if (conv_prev && semi_converged(conv_prev, tol)) return;
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   double dmax = 0.0, emax = 0.0;
   if (s < (uint32_t)g.V) {
@@ -339,16 +361,18 @@ template <typename G, typename T, int d>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_semi_iter_t(const T* __restrict__ Uc, const T* __restrict__ Ut_in, const T* __restrict__ E,
               const T* __restrict__ F2, const T* __restrict__ J, T* __restrict__ Et, T* __restrict__ Ut_out,
-              double* __restrict__ conv, Geom g, StepConst c, double omega) {
-  semi_iter_body<G, T, false, d>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c, omega);
+              double* __restrict__ conv, const double* __restrict__ conv_prev, double tol, Geom g, StepConst c,
+              double omega) {
+  semi_iter_body<G, T, false, d>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
 }
 template <typename G, typename T, bool HOP>
 __global__ void __launch_bounds__(256) k_semi_iter_z(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
                                                      const T* __restrict__ E, const T* __restrict__ F2,
                                                      const T* __restrict__ J, T* __restrict__ Et,
-                                                     T* __restrict__ Ut_out, double* __restrict__ conv, Geom g,
+                                                     T* __restrict__ Ut_out, double* __restrict__ conv,
+                                                     const double* __restrict__ conv_prev, double tol, Geom g,
                                                      StepConst c, double omega) {
-  semi_iter_body<G, T, HOP, 2>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c, omega);
+  semi_iter_body<G, T, HOP, 2>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
 }
 
 template <typename G, typename T>
@@ -381,14 +405,22 @@ void launch_semi_keep(const T* E, const T* J, T* Ep, const Geom& g, hipStream_t 
 }
 
 template <typename G, typename T>
-void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, const Geom& g, const StepConst& c, hipStream_t st) {
+void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, bool commit, const Geom& g, const StepConst& c,
+                     hipStream_t st) {
   const int bs = 256;
-  hipLaunchKernelGGL((k_semi_hop<G, T>), dim3((unsigned)((g.V + bs - 1) / bs)), dim3(bs), 0, st, U, rhoA, rhoB, J, g, c);
+  const dim3 grid((unsigned)((g.V + bs - 1) / bs));
+  if (commit) hipLaunchKernelGGL((k_semi_hop<G, T, true>), grid, dim3(bs), 0, st, U, rhoA, rhoB, J, g, c);
+  else hipLaunchKernelGGL((k_semi_hop<G, T, false>), grid, dim3(bs), 0, st, U, rhoA, rhoB, J, g, c);
+}
+
+void launch_zero(double* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
 }
 
 template <typename G, typename T>
 void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
-                      double* conv, const Geom& g, const StepConst& c, hipStream_t st) {
+                      double* conv, const double* conv_prev, double tol, const Geom& g, const StepConst& c,
+                      hipStream_t st) {
   const int bs = 256;
   // Under-relaxation of the fixed-point map E -> E(t-dt/2) + dt (F2 + f1(U, U(E)) + j).  Its
   // linearisation is implicit only in the slice-averaged transverse terms, with eigenvalues in
@@ -398,16 +430,16 @@ void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, cons
   const double omega = 1.0 / (1.0 + 2.0 * c.dt * c.dt / (c.a[0] * c.a[0]));
   const dim3 grid((unsigned)((g.V + bs - 1) / bs));
   // one launch per direction: a kernel holds only that direction's terms
-  hipLaunchKernelGGL((k_semi_iter_t<G, T, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c,
-                     omega);
-  hipLaunchKernelGGL((k_semi_iter_t<G, T, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g, c,
-                     omega);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
+                     conv_prev, tol, g, c, omega);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
+                     conv_prev, tol, g, c, omega);
   if (c.hop)
-    hipLaunchKernelGGL((k_semi_iter_z<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g,
-                       c, omega);
+    hipLaunchKernelGGL((k_semi_iter_z<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
+                       conv_prev, tol, g, c, omega);
   else
-    hipLaunchKernelGGL((k_semi_iter_z<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv, g,
-                       c, omega);
+    hipLaunchKernelGGL((k_semi_iter_z<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
+                       conv_prev, tol, g, c, omega);
 }
 
 template <typename G, typename T>
@@ -422,9 +454,9 @@ void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
   template void launch_semi_begin<G, T>(const T*, const T*, const T*, const T*, T*, T*, T*, const Geom&,        \
                                         const StepConst&, \
                                         hipStream_t);                                                          \
-  template void launch_semi_hop<G, T>(const T*, T*, T*, T*, const Geom&, const StepConst&, hipStream_t);       \
+  template void launch_semi_hop<G, T>(const T*, T*, T*, T*, bool, const Geom&, const StepConst&, hipStream_t); \
   template void launch_semi_iter<G, T>(const T*, const T*, const T*, const T*, const T*, T*, T*, double*,      \
-                                       const Geom&, const StepConst&, hipStream_t);                            \
+                                       const double*, double, const Geom&, const StepConst&, hipStream_t);     \
   template void launch_copy<G, T>(const T*, T*, int64_t, hipStream_t);
 GL_SEMI_INST(Su2<double>, double)
 GL_SEMI_INST(Su3<double>, double)

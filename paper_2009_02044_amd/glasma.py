@@ -249,6 +249,36 @@ class Batch:
     def run(self, steps, graph_chunk=16):
         self._check(lib.glasma_batch_run(self.b, int(steps), int(graph_chunk)), self.b)
 
+    def classes(self):
+        """N_z classes of the events: list of (N_z, number of events), ascending."""
+        n = len(self.events)
+        k = C.c_int32()
+        nz = (C.c_int32 * n)()
+        cnt = (C.c_int32 * n)()
+        self._check(lib.glasma_batch_classes(self.b, C.byref(k), nz, cnt), self.b)
+        return [(int(nz[i]), int(cnt[i])) for i in range(k.value)]
+
+    def observe(self, n_grid, per_event=False):
+        """Event-averaged T^{mu nu}(z) (glasma_batch_observe), device float64 tensors:
+        {"class": {N_z: (4, N_z)}, "grid": (4, n_grid)} and, with per_event, the events'
+        observables buffers (one flat tensor, events in order).  Asynchronous."""
+        cls = self.classes()
+        f = dict(dtype=torch.float64, device=self.device)
+        cbuf = torch.empty(sum(4 * nz for nz, _ in cls), **f)
+        gbuf = torch.empty(4 * int(n_grid), **f)
+        pe = torch.empty(sum(4 * lat.nz + _lib.OBS_NSCALARS for lat in self.events), **f) if per_event else None
+        self._check(lib.glasma_batch_observe(self.b, int(n_grid), C.c_void_p(cbuf.data_ptr()),
+                                             C.c_void_p(gbuf.data_ptr()),
+                                             C.c_void_p(pe.data_ptr()) if pe is not None else None), self.b)
+        out, o = {}, 0
+        for nz, _ in cls:
+            out[nz] = cbuf[o:o + 4 * nz].view(4, nz)
+            o += 4 * nz
+        r = {"class": out, "grid": gbuf.view(4, int(n_grid))}
+        if per_event:
+            r["per_event"] = pe
+        return r
+
     def set_tiling(self, sites_per_item, grid):
         self._check(lib.glasma_batch_set_tiling(self.b, int(sites_per_item), int(grid)), self.b)
 

@@ -124,3 +124,45 @@ def test_graph_replays_match_direct_launches():
             assert sa["step"] == sb["step"] == 2 * (rep + 1)
             for k in ("U", "E", "rhoA", "rhoB"):
                 assert np.array_equal(sa[k], sb[k]), (rep, e, k)
+
+
+def test_batch_event_average_on_the_device():
+    """glasma_batch_observe: the per-N_z-class averages and the common z / N_z grid equal the
+    mean of the events' own observables (glasma_observables, one by one), and each
+    per-event buffer equals that event's observables."""
+    pkg = lattice_or_skip()
+    shapes = [(16, 4), (24, 6), (16, 5), (32, 4), (24, 4)]
+    say("case: batch event average", shapes)
+    evs = []
+    for e, (nz, nt) in enumerate(shapes):
+        w = synth.Workload(f"ev{e}", nc=3, nz=nz, nt=nt, mu=0.4, sigma=1.5, seed=4300 + e)
+        evs.append((w, synth.mv_charges(w.seed, 3, nt, w.mu, w.a_T)))
+    b = pkg.Batch(3, shapes, fp=64, reunit_every=0)
+    for (w, rho), lat in zip(evs, b.events):
+        _init(lat, w, rho)
+    b.run(7, graph_chunk=0)
+    n_grid = 8
+    r = b.observe(n_grid, per_event=True)
+    b.stream.synchronize()
+    ones = [lat.observables()["tmunu_z"] for lat in b.events]
+    assert [c for c, _ in b.classes()] == [16, 24, 32]
+    assert dict(b.classes()) == {16: 2, 24: 2, 32: 1}
+    for nz, got in r["class"].items():
+        ref = np.mean([o for o, (w, _) in zip(ones, evs) if w.nz == nz], axis=0)
+        np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+    grid = np.zeros((4, n_grid))
+    for o in ones:
+        nz = o.shape[1]
+        bins = (np.arange(nz) * n_grid) // nz
+        grid += np.stack([np.bincount(bins, weights=o[q], minlength=n_grid) / np.bincount(bins) for q in range(4)])
+    grid /= len(ones)
+    np.testing.assert_allclose(r["grid"].cpu().numpy(), grid, rtol=1e-12, atol=1e-15 * np.abs(grid).max())
+    pe = r["per_event"].cpu().numpy()
+    off = 0
+    for o in ones:
+        nz = o.shape[1]
+        np.testing.assert_allclose(pe[off:off + 4 * nz].reshape(4, nz), o, rtol=1e-13, atol=1e-300)
+        off += 4 * nz + 8
+    from paper_2009_02044_amd import GlasmaError
+    with pytest.raises(GlasmaError):
+        b.observe(17)       # more bins than the smallest N_z

@@ -71,8 +71,14 @@ def test_semi_implicit_reaching_max_iter():
     st = si.charges_for_scheme(st)
     lat = pkg.Lattice(nc=3, nz=w.nz, nt=w.nt, a_T=w.a_T, a_L=w.a_L, dt=1.0, scheme=1, max_iter=1, tol=1e-15)
     lat.init_state(*to_comp(st), step0=0)
+    before = lat.get_state()
+    # at dt = a_L every step hops: the failed solve must not have moved the charges
     assert code_of(lambda: lat.step(1)) == E_NOCONV
     assert lat.last_iterations == 1
+    after = lat.get_state()
+    assert after["step"] == before["step"] == 0
+    for k in ("U", "E", "rhoA", "rhoB"):
+        assert np.array_equal(after[k], before[k]), k
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
@@ -92,7 +98,12 @@ def test_non_finite_fields_are_reported(scheme):
                       max_iter=50, tol=1e-12 if scheme == 1 else 0.0)
     lat.init_state(U, E, rA, rB, step0=0)
     if scheme == 1:
+        before = lat.get_state()
         assert code_of(lambda: lat.step(1)) == E_NONFINITE
+        after = lat.get_state()
+        assert after["step"] == 0
+        for k in ("U", "rhoA", "rhoB"):
+            assert np.array_equal(after[k], before[k]), k
     else:
         lat.step(2)
         assert code_of(lambda: lat.observables()) == E_NONFINITE

@@ -196,35 +196,75 @@ def test_fp32_precision_form_against_fp64_oracle():
     say("fp32 worst observable error over 48 steps", worst)
 
 
-def test_full_size_plain_su3_sampled():
+def _hop_at_site(U_at, rA_at, rB_at, site, dims, p):
+    """The oracle's CPIC hop (lattice.cpic_hop) evaluated on the two-layer column (z, z + 1)
+    at (y, x): its layer-0 values are the hop's j_z(x) and rho_A'(x), its layer-1 value is
+    rho_B'(x + z) (both rules read only U_z(x) and the charges at x and x + z).  U_at(i, pos),
+    rA_at(pos), rB_at(pos) return matrices at a lattice position."""
+    z, y, x = site
+    nz = dims[0]
+    col = [((z + k) % nz, y, x) for k in (0, 1)]
+    Uc = np.stack([np.stack([U_at(i, q) for q in col]) for i in range(3)])[:, :, None, None]
+    rA = np.stack([rA_at(q) for q in col])[:, None, None]
+    rB = np.stack([rB_at(q) for q in col])[:, None, None]
+    rA_new, rB_new, j = lattice.cpic_hop(Uc, rA, rB, p)
+    return j[2, 0, 0, 0], rA_new[0, 0, 0], rB_new[1, 0, 0]
+
+
+@pytest.mark.parametrize("hop", [False, True])
+def test_full_size_plain_su3_sampled(hop):
     """SU(3) FP64 at the full 512 x 64 x 64 size in the benchmark's launch configuration:
-    MV initial state on the GPU, 5 steps; properties that hold at any size (Gauss
-    law, unitarity), and the E update at sampled sites recomputed by the oracle."""
+    MV initial state on the GPU, then one step (the fifth, no hop, or the sixth, a hop step
+    at dt = a_L/2) compared at sampled sites with the oracle: the E update of all three
+    directions from the oracle's single-site force, and on the hop step the current j_z in
+    E_z and both charge populations after the oracle's hop (lattice.cpic_hop) with its
+    parallel transport; Gauss law and unitarity over the whole lattice."""
     pkg = lattice_or_skip()
     w = synth.PLAIN_SU3
-    say("case: full-size su3 512x64x64")
+    say("case: full-size su3 512x64x64, hop", hop)
     rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
     lat = new_lattice(pkg, w)
     lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma)
-    lat.step(4)
-    before = from_comp(lat.get_state(), 3, (w.nz, w.nt, w.nt), lattice.Params(3, w.a_T, w.a_L, w.dt))
+    lat.step(5 if hop else 4)
+    dims = (w.nz, w.nt, w.nt)
+    before = from_comp(lat.get_state(), 3, dims, lattice.Params(3, w.a_T, w.a_L, w.dt))
     o = lat.observables()
     assert o["gauss_rel"] < 1e-12 and o["unitarity"] < 1e-13
     lat.step(1)
     after = lat.get_state()
+    o = lat.observables()
+    assert o["gauss_rel"] < 1e-12 and o["unitarity"] < 1e-13
     g = synth.rng(7)
     sites = [(int(g.integers(w.nz)), int(g.integers(w.nt)), int(g.integers(w.nt))) for _ in range(24)]
-    sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 5, w.nt - 1)]
+    # the nuclei (z = 128, 384) and the z seam
+    sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 5, w.nt - 1), (w.nz // 4 + 3, 9, 17),
+              (3 * w.nz // 4 - 2, 40, 0), (3 * w.nz // 4, 63, 31)]
     p = before.params
-    hop = lattice.is_hop_step(before.step, p)
-    assert not hop            # hops happen on odd steps at dt = a_L/2
+    assert lattice.is_hop_step(before.step, p) == hop
     from oracle import su
+    U_at = lambda i, q: before.U[i][q]
+    rA_at = lambda q: before.rhoA[q]
+    rB_at = lambda q: before.rhoB[q]
+    rho_scale = max(np.abs(before.rhoA).max(), np.abs(before.rhoB).max())
+    worst = {"E": 0.0, "rhoA": 0.0, "rhoB": 0.0}
     for (z, y, x) in sites:
         F = lattice.force_at_site(before.U, p.a, (z, y, x))
         E_ref = before.E[:, z, y, x] + p.dt * F
+        if hop:
+            jz, rA_new, rB_new = _hop_at_site(U_at, rA_at, rB_at, (z, y, x), dims, p)
+            E_ref[2] = E_ref[2] + p.dt * jz
+            s_a = (z * w.nt + y) * w.nt + x
+            s_b = (((z + 1) % w.nz) * w.nt + y) * w.nt + x
+            for name, got, ref in (("rhoA", after["rhoA"][:, s_a], rA_new), ("rhoB", after["rhoB"][:, s_b], rB_new)):
+                e = np.abs(su.from_components(got, 3) - ref).max() / rho_scale
+                worst[name] = max(worst[name], e)
+                assert e < 1e-12, (name, (z, y, x), e)
         s = (z * w.nt + y) * w.nt + x
         E_got = su.from_components(after["E"][:, :, s], 3)
-        np.testing.assert_allclose(E_got, E_ref, atol=1e-12 * max(1.0, np.abs(E_ref).max()))
+        e = np.abs(E_got - E_ref).max() / max(1.0, np.abs(E_ref).max())
+        worst["E"] = max(worst["E"], e)
+        assert e < 1e-12, ((z, y, x), e)
+    say("worst sampled errors", worst)
 
 
 class _SampledLinks:
@@ -249,35 +289,41 @@ class _SampledLinks:
         return self.cache[key]
 
 
-@pytest.mark.parametrize("fp", [64, 32])
-def test_full_size_precision_workload_sampled(fp):
+@pytest.mark.parametrize("fp,hop", [(64, False), (32, False), (64, True), (32, True)])
+def test_full_size_precision_workload_sampled(fp, hop):
     """SU(3) at the precision form's full size, 2048 x 192 x 192 (sigma = 16), FP64 and
-    FP32 (reunitarisation every 8 steps): MV initial state on the GPU, 5 steps, Gauss law and
-    unitarity over the whole lattice, and the E update of the fifth (non-hop) step at
-    sampled sites recomputed by the oracle from the stored links (FP32: the stored FP32
-    values, so the bar is FP32 rounding of the update)."""
+    FP32 (reunitarisation every 8 steps): MV initial state on the GPU, Gauss law and
+    unitarity over the whole lattice, and the E update of the fifth (non-hop) or sixth (hop)
+    step at sampled sites recomputed by the oracle from the stored links (FP32: the stored
+    FP32 values, so the bar is FP32 rounding of the update); on the hop step also the
+    current in E_z and both charge populations after the oracle's hop."""
     import torch
     pkg = lattice_or_skip()
     w = synth.PRECISION_SU3
-    say("case: full-size precision workload su3 2048x192x192 fp", fp)
+    say("case: full-size precision workload su3 2048x192x192 fp", fp, "hop", hop)
     rA, rB = synth.mv_charges(w.seed, 3, w.nt, w.mu, w.a_T)
     lat = new_lattice(pkg, w, fp=fp, reunit_every=8 if fp == 32 else 0)
     lat.init_mv(rA, rB, m_ir=w.m_ir, uv_cut=w.uv_cut, sigma=w.sigma)
-    lat.step(4)
+    lat.step(5 if hop else 4)
     o = lat.observables()
     say("gauss_rel", o["gauss_rel"], "unitarity", o["unitarity"])
     assert o["gauss_rel"] < (1e-12 if fp == 64 else 1e-5) and o["unitarity"] < (1e-13 if fp == 64 else 1e-5)
     p = lattice.Params(3, w.a_T, w.a_L, w.dt)
-    assert not lattice.is_hop_step(lat.step_count, p)
+    assert lattice.is_hop_step(lat.step_count, p) == hop
     f = dict(dtype=torch.float64, device=lat.device)
     U0 = torch.empty(3, lat.r, lat.V, **f)
     E0 = torch.empty(3, lat.ng, lat.V, **f)
+    rA0 = torch.empty(lat.ng, lat.V, **f) if hop else None
+    rB0 = torch.empty(lat.ng, lat.V, **f) if hop else None
     from paper_2009_02044_amd._lib import lib
     import ctypes as C
-    lat._chk(lib.glasma_get_state_device(lat.ctx, C.c_void_p(U0.data_ptr()), C.c_void_p(E0.data_ptr()), None, None))
+    vp = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    lat._chk(lib.glasma_get_state_device(lat.ctx, vp(U0), vp(E0), vp(rA0), vp(rB0)))
     lat.step(1)
     E1 = torch.empty(3, lat.ng, lat.V, **f)
-    lat._chk(lib.glasma_get_state_device(lat.ctx, None, C.c_void_p(E1.data_ptr()), None, None))
+    rA1 = torch.empty(lat.ng, lat.V, **f) if hop else None
+    rB1 = torch.empty(lat.ng, lat.V, **f) if hop else None
+    lat._chk(lib.glasma_get_state_device(lat.ctx, None, vp(E1), vp(rA1), vp(rB1)))
     # the field scale: sites far from the nuclei carry exponentially small E whose
     # digits are rounding noise on either side (bar as max(|ref|, RMS of the field))
     rms = float(torch.sqrt(torch.mean(E1 * E1)))
@@ -289,10 +335,23 @@ def test_full_size_precision_workload_sampled(fp):
     sites += [(0, 0, 0), (w.nz - 1, w.nt - 1, w.nt - 1), (w.nz // 4, 7, w.nt - 1), (3 * w.nz // 4, 0, 100)]
     from oracle import su
     worst = 0.0
+    if hop:
+        def charge_at(t):
+            return lambda q: su.from_components(t[:, (q[0] * w.nt + q[1]) * w.nt + q[2]].cpu().numpy(), 3)
+        rho_scale = max(float(rA0.abs().max()), float(rB0.abs().max()))
+        sites += [(w.nz // 4 + 5, 3, 3), (3 * w.nz // 4 - 6, 150, 191)]   # inside the nuclei
     for (z, y, x) in sites:
         s = (z * w.nt + y) * w.nt + x
         F = lattice.force_at_site(Us, p.a, (z, y, x))
         E_ref = su.from_components(E0[:, :, s].cpu().numpy(), 3) + p.dt * F
+        if hop:
+            jz, rA_new, rB_new = _hop_at_site(lambda i, q: Us[(i,) + tuple(q)], charge_at(rA0), charge_at(rB0),
+                                              (z, y, x), dims, p)
+            E_ref[2] = E_ref[2] + p.dt * jz
+            s_b = (((z + 1) % w.nz) * w.nt + y) * w.nt + x
+            for name, t, sg, ref in (("rhoA", rA1, s, rA_new), ("rhoB", rB1, s_b, rB_new)):
+                e = np.abs(su.from_components(t[:, sg].cpu().numpy(), 3) - ref).max() / rho_scale
+                assert e < (1e-12 if fp == 64 else 1e-6), (name, (z, y, x), e)
         E_got = su.from_components(E1[:, :, s].cpu().numpy(), 3)
         scale = max(np.abs(E_ref).max(), rms)
         err = np.abs(E_got - E_ref).max() / scale

@@ -36,10 +36,26 @@ def test_semi_implicit_parity(nc, nz, nt, dt):
         assert max(errs.values()) < 1e-10, (s, errs)
     gst = from_comp(lat.get_state(), nc, (nz, nt, nt), p)
     assert si.gauss_mod_residual(gst) < 1e-12
+    # observables at integer time with E averaged over the two half steps (the definition
+    # the leapfrog uses): E(t + dt/2) from the oracle's own solve of the next step
+    st_next = si.semi_implicit_step(st, tol=1e-15)
+    oo = observables.observables(st, E_new=st_next.E)
     go = lat.observables()
-    oo = observables.observables(st, E_new=st.E)
     sl = oo["tmunu_z"]
-    assert np.max(np.abs(go["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True)) < 1e-9
+    err = np.max(np.abs(go["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True))
+    say(" T^{mu nu} slices (averaged time level)", err, "H", abs(go["energy"] - oo["energy"]) / oo["energy"])
+    assert err < 1e-9
+    assert abs(go["energy"] - oo["energy"]) < 1e-10 * abs(oo["energy"])
+    # the one-sided level (E(t - dt/2) for both halves) differs by O(dt): the test sees it
+    one_sided = observables.observables(st, E_new=st.E)["tmunu_z"]
+    assert np.max(np.abs(one_sided - sl) / np.abs(sl).max(axis=1, keepdims=True)) > 1e-6
+    # observing step: the same numbers from the solve that the step itself commits
+    obs = lat.obs_buffer()
+    lat.step_observe(1, obs)
+    o2 = pkg.Lattice.unpack_obs(obs, nz)
+    assert np.max(np.abs(o2["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True)) < 1e-9
+    errs = state_errs(lat.get_state(), st_next)
+    assert max(errs.values()) < 1e-10, errs
 
 
 def test_semi_implicit_init_mv_charges():
@@ -82,7 +98,7 @@ def test_semi_implicit_fp32_against_fp64_oracle(nc):
         assert max(errs.values()) < 1e-4, (s, errs)
     say(" worst per-component error over 6 steps", worst)
     go = lat.observables()
-    oo = observables.observables(st, E_new=st.E)
+    oo = observables.observables(st, E_new=si.semi_implicit_step(st, tol=1e-15).E)
     sl = oo["tmunu_z"]
     err = np.max(np.abs(go["tmunu_z"] - sl) / np.abs(sl).max(axis=1, keepdims=True))
     say(" T^{mu nu} slices", err)
