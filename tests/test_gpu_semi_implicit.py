@@ -145,3 +145,76 @@ def test_semi_implicit_dispersion_on_the_gpu(k, dt):
         np.testing.assert_allclose(got, expect, rtol=1e-7, atol=1e-8)
     if k[0] == 0 and dt == 1.0:
         assert abs(np.arccos(expect) - kz) < 1e-12
+
+
+@pytest.mark.parametrize("k_int,dt", [((1, 2, 3), 1.0), ((2, 1, 5), 0.5), ((1, 1, 0), 1.0)])
+def test_full_linear_symbol_on_the_gpu(k_int, dt):
+    """Every physical polarisation of a general wave vector (the A_z-polarised wave of the
+    E_L equation included) propagates under the GPU's semi-implicit step with the cos(w dt)
+    of the hand-derived symbol (tests/_symbol.py)."""
+    pkg = lattice_or_skip()
+    from _symbol import modes
+    from test_oracle_semi_implicit import _wave_state, _link_fields, _recurrence_c
+    nc, dims, a = 2, (12, 6, 6), (4.0, 4.0, 1.0)     # the library's lattices are nt x nt transverse
+    say(f"case: semi-implicit symbol k {k_int} dt {dt}")
+    k = tuple(2 * np.pi * k_int[i] / (dims[2 - i] * a[i]) for i in range(3))
+    cs, vs = modes(k, a, dt)
+    p = lattice.Params(nc=nc, a_T=a[0], a_L=a[2], dt=dt)
+    checked = 0
+    for m in range(3):
+        c, v = cs[m], vs[:, m]
+        if abs(c - 1.0) < 1e-9:
+            continue
+        st, A0 = _wave_state(nc, dims, a, k_int, v / np.abs(v).max(), 1e-6, c, dt)
+        lat = pkg.Lattice(nc=nc, nz=dims[0], nt=dims[1], a_T=a[0], a_L=a[2], dt=dt, fp=64, scheme=1,
+                          max_iter=100, tol=1e-15)
+        lat.init_state(*to_comp(st), step0=0)
+        A = [A0]
+        for _ in range(4):
+            lat.step(1)
+            A.append(_link_fields(from_comp(lat.get_state(), nc, dims, p), a, nc))
+        got = _recurrence_c(np.array(A))
+        say(f"  mode {m}: c {c:.10f} GPU {got:.10f}")
+        assert abs(got - c) < 1e-6
+        checked += 1
+    assert checked == 2
+
+
+def test_cherenkov_lone_nucleus_on_the_gpu():
+    """Numerical Cherenkov radiation on a 256 x 16 x 16 SU(3) lattice: one nucleus (dilute MV
+    charges, sigma = 2 a_L) moving +z at the speed of light.  Leapfrog at dt = a_L/2: the
+    energy in the 64 layers that end 5 sigma behind the nucleus grows with t and the total
+    grows.  Semi-implicit at dt = a_L: the same fraction stays orders of magnitude smaller
+    and the total stays put.  Semi-implicit at dt = a_L/2 is dispersive along z like the
+    leapfrog and radiates like it."""
+    pkg = lattice_or_skip()
+    nc, nz, nt, aT, sigma, mu, zB = 3, 256, 16, 4.0, 2.0, 0.05, 32.0
+    rA, rB = synth.mv_charges(77, nc, nt, mu, aT)
+    rA = np.zeros_like(rA)
+    z = np.arange(nz)
+    res = {}
+    for scheme, dt in ((0, 0.5), (1, 1.0), (1, 0.5)):
+        say(f"case: lone nucleus scheme {scheme} dt {dt}")
+        lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=aT, a_L=1.0, dt=dt, fp=64, scheme=scheme, max_iter=300,
+                          tol=1e-12)
+        lat.init_mv(rA, rB, m_ir=0.2, uv_cut=0.0, sigma=sigma, zA=0.75 * nz, zB=zB)
+        per = int(round(16 / dt))
+        frac, H = [], []
+        for k in range(11):
+            o = lat.observables()
+            eps = o["tmunu_z"][0]
+            zc = zB + 16 * k
+            win = (z > zc - 5 * sigma - 64) & (z < zc - 5 * sigma)
+            frac.append(eps[win].sum() / eps.sum())
+            H.append(o["energy"])
+            if k < 10:
+                lat.step(per)
+        res[(scheme, dt)] = (np.array(frac), np.array(H))
+        say("  behind/total at t = 64..160:", " ".join(f"{f:.1e}" for f in frac[4:]),
+            f" H(t)/H(0) {H[-1] / H[0]:.5f}")
+    lf, Hl = res[(0, 0.5)]
+    sm, Hs = res[(1, 1.0)]
+    s5, _ = res[(1, 0.5)]
+    assert np.all(np.diff(lf[4:]) > 0) and lf[-1] > 2e-2 and Hl[-1] / Hl[0] > 1.05
+    assert np.all(sm[4:] < 1e-3 * lf[4:]) and abs(Hs[-1] / Hs[0] - 1) < 3e-3
+    assert np.all(s5[4:] > 0.5 * lf[4:])

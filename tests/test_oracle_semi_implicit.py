@@ -159,3 +159,145 @@ def test_potential_symmetric_in_the_two_slices():
     f1, f2 = si.f_forces(U0, U1, a)
     g1, _ = si.f_forces(U1, U0, a)
     np.testing.assert_allclose(f2, g1, atol=1e-13)
+
+
+def _wave_state(nc, dims, a, k_int, vec, amp, c, dt):
+    """Small-amplitude single-colour plane wave A_i(x) = amp Re[vec_i exp(i k.x)] on the links
+    (base-site convention), in a cos(w t) phase: A(t - dt) = c A(t), so E(t - dt/2) =
+    (1 - c) A(t) / dt.  k_int: integer wave numbers over the lattice (n_x, n_y, n_z)."""
+    nz, ny, nx = dims
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phase = 2 * np.pi * (k_int[0] * xx / nx + k_int[1] * yy / ny + k_int[2] * zz / nz)
+    A = np.stack([amp * np.real(vec[i] * np.exp(1j * phase)) for i in range(3)])
+    ng = nc * nc - 1
+    alg = np.zeros((3,) + dims + (ng,))
+    alg[..., ng - 1] = A
+    U = su.expi(su.from_components(alg * np.array(a)[:, None, None, None, None], nc))
+    E = su.from_components(alg * (1.0 - c) / dt, nc)
+    p = lattice.Params(nc=nc, a_T=a[0], a_L=a[2], dt=dt)
+    z = np.zeros(dims + (nc, nc), complex)
+    return lattice.State(U, E, z, z.copy(), 0, p), A
+
+
+def _recurrence_c(A):
+    """c of A(n + 1) + A(n - 1) = 2 c A(n), least squares over the steps and sites of a
+    field history A[n] (well conditioned also where one A(n) nearly vanishes)."""
+    num = sum(np.sum((A[n + 1] + A[n - 1]) * A[n]) for n in range(1, len(A) - 1))
+    den = sum(2 * np.sum(A[n] * A[n]) for n in range(1, len(A) - 1))
+    return num / den
+
+
+def _link_fields(st, a, nc):
+    return np.stack([su.to_components(su.logi(st.U[i]))[..., nc * nc - 2] / a[i] for i in range(3)])
+
+
+@pytest.mark.parametrize("k_int,dt", [((1, 2, 3), 1.0), ((1, 1, 5), 0.5), ((2, 1, 2), 1.0), ((1, 0, 0), 1.0)])
+def test_full_linear_symbol_general_k(k_int, dt):
+    """Every polarisation of a general wave vector, including the A_z-polarised wave of the
+    E_L equation with its time-averaged transverse Laplacian: the oracle's semi-implicit step
+    propagates each physical eigenmode of the hand-derived symbol (tests/_symbol.py) with
+    A(t + dt) + A(t - dt) = 2 c A(t), c its generalized eigenvalue."""
+    from _symbol import modes
+    nc = 2
+    dims = (12, 4, 6)
+    a = (4.0, 4.0, 1.0)
+    k = tuple(2 * np.pi * k_int[i] / (dims[2 - i] * a[i]) for i in range(3))
+    cs, vs = modes(k, a, dt)
+    checked = 0
+    for m in range(3):
+        c, v = cs[m], vs[:, m]
+        if abs(c - 1.0) < 1e-9:         # the static gauge mode
+            continue
+        st, A0 = _wave_state(nc, dims, a, k_int, v / np.abs(v).max(), 1e-6, c, dt)
+        A = [A0]
+        for _ in range(4):
+            st = si.semi_implicit_step(st, tol=1e-15)
+            A.append(_link_fields(st, a, nc))
+        assert abs(_recurrence_c(np.array(A)) - c) < 1e-6, (m, c, _recurrence_c(np.array(A)))
+        checked += 1
+    assert checked == 2
+    if k_int == (1, 0, 0):
+        # pure A_z wave along x: c = 1 / (1 + dt^2 K_x / 2)
+        Kx = (2 / a[0]) ** 2 * np.sin(k[0] * a[0] / 2) ** 2
+        assert np.isclose(cs[np.argmin(np.abs(cs - 1 / (1 + dt ** 2 * Kx / 2)))], 1 / (1 + dt ** 2 * Kx / 2),
+                          rtol=1e-12)
+
+
+def test_symbol_stability_boundary_at_dt_equal_a_L():
+    """The symbol has |c| <= 1 for every k of a 7^3 grid over the Brillouin zone at dt = a_L
+    (a_T = 4 a_L and a_T = a_L) and |c| > 1 for some k just above it, so the scheme is stable
+    exactly up to dt = a_L (the method itself needs dt <= a_L: a charge hops at most one cell
+    per step, so the oracle cannot be run beyond it).  The mode at the corner of the zone,
+    the first to go unstable, reaches c = -1 at dt = a_L: the oracle follows its symbol at
+    dt = 0.98 a_L and keeps it bounded at dt = a_L."""
+    from _symbol import modes
+    for aT in (4.0, 1.0):
+        a = (aT, aT, 1.0)
+        for dt, stable in ((1.0, True), (1.05, False)):
+            worst = 0.0
+            for nx in range(7):
+                for ny in range(7):
+                    for nzk in range(7):
+                        k = (np.pi * nx / 6 / a[0], np.pi * ny / 6 / a[1], np.pi * nzk / 6)
+                        worst = max(worst, np.abs(modes(k, a, dt)[0]).max())
+            assert (worst <= 1 + 1e-12) == stable, (aT, dt, worst)
+    nc, dims, a = 2, (2, 2, 2), (4.0, 4.0, 1.0)
+    k_int = (1, 1, 1)
+    k = (np.pi / a[0], np.pi / a[1], np.pi)
+    for dt in (0.98, 1.0):
+        cs, vs = modes(k, a, dt)
+        m = int(np.argmin(cs))
+        c = cs[m]
+        st, A0 = _wave_state(nc, dims, a, k_int, vs[:, m] / np.abs(vs[:, m]).max(), 1e-8, c, dt)
+        A = [A0]
+        for _ in range(12):
+            st = si.semi_implicit_step(st, tol=1e-15)
+            A.append(_link_fields(st, a, nc))
+        A = np.array(A)
+        amp = np.abs(A).reshape(len(A), -1).max(axis=1)
+        if dt < 1:
+            assert -1 < c < -0.9 and abs(_recurrence_c(A) - c) < 1e-6
+        else:
+            # c = -1: the cos(w t) start stays an alternating pattern of constant amplitude
+            assert abs(c + 1) < 1e-12 and max(amp) < 1.01 * amp[0]
+
+
+def test_cherenkov_lone_nucleus():
+    """Numerical Cherenkov radiation (Sec. 3; Sec. 5): a lone nucleus (dilute MV charges,
+    sigma = 2 a_L, moving +z at the speed of light) leaves energy behind it under the
+    leapfrog at dt = a_L/2, growing with time along with the total field energy (the moving
+    source feeds the lattice modes slower than light); under the semi-implicit scheme at
+    dt = a_L, dispersion-free along z, the energy behind it stays orders of magnitude smaller
+    and the total stays put.  Energy behind = the eps slices over the 20 layers ending
+    5 sigma behind the nucleus centre, as a fraction of the total."""
+    nc, nz, nt, sigma, mu, zB = 2, 48, 4, 2.0, 0.05, 8.0
+    rA, rB = synth.mv_charges(77, nc, nt, mu, 4.0)
+    rA = np.zeros_like(rA)
+    from oracle import observables
+    curves, Hs = {}, {}
+    for scheme, dt in ((0, 0.5), (1, 1.0)):
+        p = lattice.Params(nc=nc, a_T=4.0, a_L=1.0, dt=dt)
+        mv = init_mv.MVParams(m_ir=0.2, uv_cut=0.0, sigma=sigma, zA=0.75 * nz, zB=zB)
+        st, _ = init_mv.initial_state(rA, rB, nz, p, mv)
+        if scheme == 1:
+            st = si.charges_for_scheme(st)
+        z = np.arange(nz)
+        frac, H = [], []
+        n = int(round(28 / dt))
+        for k in range(n + 1):
+            nxt = si.semi_implicit_step(st, tol=1e-12) if scheme else lattice.leapfrog_step(st)
+            if k % int(round(4 / dt)) == 0:
+                sl, h = observables.tmunu_slices(st, E_new=nxt.E)
+                zc = zB + k * dt
+                win = (z > zc - 5 * sigma - 20) & (z < zc - 5 * sigma)
+                frac.append(sl[0][win].sum() / sl[0].sum())
+                H.append(h)
+            st = nxt
+        curves[scheme], Hs[scheme] = np.array(frac), np.array(H)
+    lf, sm = curves[0], curves[1]
+    # leapfrog: the trailing energy grows from t = 8 on and the total grows
+    assert np.all(np.diff(lf[2:]) > 0) and lf[-1] > 3e-3
+    assert Hs[0][-1] / Hs[0][0] > 1.03
+    # semi-implicit: trailing energy below 3% of the leapfrog's at every t >= 8, total within 1e-3
+    assert np.all(sm[2:] < 0.03 * lf[2:]) and sm.max() < 2e-4
+    assert abs(Hs[1][-1] / Hs[1][0] - 1) < 1e-3
