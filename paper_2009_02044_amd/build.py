@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libglasma.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "step.hip", "observe.hip", "init.hip", "semi.hip", "adjoint.hip", "bi.hip"]
+SOURCES = ["capi.hip", "step.hip", "observe.hip", "init.hip", "semi.hip", "semi_march.hip", "adjoint.hip",
+           "bi.hip"]
 
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950",

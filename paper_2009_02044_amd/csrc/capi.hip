@@ -101,9 +101,9 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Work buffer: [general region: initial conditions or observable reductions]
 // then, for the semi-implicit scheme, [U(t-dt) | trial links | trial E | f1(U(t), U(t-dt)) | dt j |
-// E of the previous step | 2 doubles].
+// E of the previous step | loops of U(t) alone (marching geometries) | convergence slots].
 struct SemiRegion {
-  size_t up, ut, et, f2, j, ep, conv, end;  // byte offsets
+  size_t up, ut, et, f2, j, ep, cache, conv, end;  // byte offsets
 };
 // convergence slots (2 doubles per iteration) of one batch of enqueued iterations
 constexpr int SEMI_SLOTS = 64;
@@ -127,7 +127,8 @@ static SemiRegion semi_region(const glasma_params* p) {
   s.f2 = s.et + align256(3 * (size_t)ng * g.Vp * e);
   s.j = s.f2 + align256(3 * (size_t)ng * g.Vp * e);
   s.ep = s.j + align256((size_t)ng * g.Vp * e);
-  s.conv = s.ep + align256(3 * (size_t)ng * g.Vp * e);
+  s.cache = s.ep + align256(3 * (size_t)ng * g.Vp * e);
+  s.conv = s.cache + (march_geometry(g) ? align256(march_cache_elems(g, p->nc) * e) : 0);
   s.end = s.conv + SEMI_SLOTS * 2 * sizeof(double);
   return s;
 }
@@ -385,7 +386,9 @@ static int semi_solve(glasma_ctx* c, const StepConst& sc, void** links) {
     T* buf[2] = {next_U<T>(c), (T*)(w + r.ut)};   // iteration k reads buf[k & 1], writes buf[(k + 1) & 1]
     launch_semi_begin<G, T>(Uc, (T*)c->b.E, c->semi_prev ? Ep : nullptr, sc.hop ? J : nullptr, Up, buf[0], Et, c->g,
                             sc, c->stream);
-    launch_semi_f1<G, T>(Uc, Up, F2, c->g, sc, c->stream);
+    T* cache = march_geometry(c->g) ? (T*)(w + r.cache) : nullptr;
+    launch_semi_f1<G, T>(Uc, Up, F2, c->g, sc, c->stream, cache);
+    launch_semi_base<G, T>((const T*)c->b.E, F2, sc.hop ? J : nullptr, c->g, c->p.dt, c->stream);
     double h[2 * SEMI_SLOTS];
     int done = 0, at = -1;
     while (done < c->p.max_iter && at < 0) {
@@ -394,8 +397,8 @@ static int semi_solve(glasma_ctx* c, const StepConst& sc, void** links) {
       launch_zero(conv, 2 * nb, c->stream);
       for (int k = 0; k < nb; ++k) {
         const int it = done + k;
-        launch_semi_iter<G, T>(Uc, buf[it & 1], (T*)c->b.E, F2, J, Et, buf[(it + 1) & 1], conv + 2 * k,
-                               k ? conv + 2 * (k - 1) : nullptr, c->p.tol, c->g, sc, c->stream);
+        launch_semi_iter<G, T>(Uc, buf[it & 1], F2, Et, buf[(it + 1) & 1], conv + 2 * k,
+                               k ? conv + 2 * (k - 1) : nullptr, c->p.tol, c->g, sc, c->stream, cache);
       }
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipMemcpyAsync(h, conv, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -80,8 +80,11 @@ template <typename G, typename T>
 void launch_reunit(T* U, const Geom& g, hipStream_t st);
 
 // Semi-implicit scheme (semi.hip)
+// f1(Uc, Uo) of every link into out; cache (may be null): the marching pass also stores
+// the loops of Uc alone there for the iterations of the step
 template <typename G, typename T>
-void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st);
+void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st,
+                    T* cache = nullptr);
 template <typename G, typename T>
 void launch_semi_begin(const T* U, const T* E, const T* Ep, const T* J, T* Up, T* Ut, T* Et, const Geom& g,
                        const StepConst& c, hipStream_t st);
@@ -92,12 +95,35 @@ void launch_semi_keep(const T* E, const T* J, T* Ep, const Geom& g, hipStream_t 
 template <typename G, typename T>
 void launch_semi_hop(const T* U, T* rhoA, T* rhoB, T* J, bool commit, const Geom& g, const StepConst& c,
                      hipStream_t st);
-// one fixed-point iteration; conv (2 doubles, zeroed before) receives max|dE|, max|E|; with
-// conv_prev (the slot of the iteration before) already converged to tol it does nothing
+// Ebase = E + dt F2 + [z] J in place over F2 (J: dt j_z on hop steps, or null)
 template <typename G, typename T>
-void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
-                      double* conv, const double* conv_prev, double tol, const Geom& g, const StepConst& c,
-                      hipStream_t st);
+void launch_semi_base(const T* E, T* F2, const T* J, const Geom& g, double dt, hipStream_t st);
+// one fixed-point iteration E' = Ebase + dt f1(Uc, Ut_in); conv (2 doubles, zeroed before)
+// receives max|dE|, max|E|; with conv_prev (the slot of the iteration before) already
+// converged to tol it does nothing
+template <typename G, typename T>
+void launch_semi_iter(const T* Uc, const T* Ut_in, const T* Ebase, T* Et, T* Ut_out, double* conv,
+                      const double* conv_prev, double tol, const Geom& g, const StepConst& c, hipStream_t st,
+                      const T* cache);
+// The marching pass (semi_march.hip) for lattices with 8 <= nt <= 64, nt dividing 64:
+// mode 0 writes f1(A, B) to it.F; mode 1 is one fixed-point iteration (A = U(t), B = the
+// trial links) with the fields of it.
+struct MarchIter {
+  const void* Ebase;
+  void* Et;
+  void* Ut_out;
+  double* conv;
+  const double* conv_prev;
+  double tol, omega;
+  void* F;
+  void* cache;   // loops of slice A alone: written by mode 0 (if not null), read by mode 1
+};
+// elements of the loop cache: 3 planes of full matrices (18 or 4 reals) per padded site
+size_t march_cache_elems(const Geom& g, int nc);
+bool march_geometry(const Geom& g);
+template <typename G, typename T>
+void launch_semi_march(const T* A, const T* B, const Geom& g, const StepConst& c, int mode, const MarchIter& it,
+                       hipStream_t st);
 void launch_zero(double* p, int n, hipStream_t st);
 template <typename G, typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);

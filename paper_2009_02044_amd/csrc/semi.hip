@@ -294,15 +294,15 @@ __device__ __forceinline__ bool semi_converged(const double* conv, double tol) {
   return conv[0] <= tol * (e > 0.0 ? e : 1e-300);
 }
 
-// One fixed-point iteration: E' = E + dt (F2 + f1(Uc, Ut_in)) + [z] dt j, Ut_out = exp(i a dt E') Uc,
-// Et <- E'; conv[0] = max |E' - Et_old| (+inf if E' is not finite), conv[1] = max |E'|
-// (component-wise).  When the previous iteration's slot conv_prev already passes the test
-// the iteration does nothing (every thread returns): the host enqueues several iterations
-// at once and reads their slots afterwards.
-template <typename G, typename T, bool HOP, int d>
+// One fixed-point iteration: E' = Ebase + dt f1(Uc, Ut_in) with Ebase = E + dt f1(Uc, U(t - dt))
+// + [z] dt j (k_semi_base), Ut_out = exp(i a dt E') Uc, Et <- E'; conv[0] = max |E' - Et_old|
+// (+inf if E' is not finite), conv[1] = max |E'| (component-wise).  When the previous
+// iteration's slot conv_prev already passes the test the iteration does nothing (every
+// thread returns): the host enqueues several iterations at once and reads their slots
+// afterwards.  (Lattices whose rows fill wavefronts use the marching pass of semi_march.hip.)
+template <typename G, typename T, int d>
 __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
-                                               const T* __restrict__ E, const T* __restrict__ F2,
-                                               const T* __restrict__ J, T* __restrict__ Et,
+                                               const T* __restrict__ Ebase, T* __restrict__ Et,
                                                T* __restrict__ Ut_out, double* __restrict__ conv,
                                                const double* __restrict__ conv_prev, double tol, const Geom& g,
                                                const StepConst& c, double omega) {
@@ -315,19 +315,12 @@ __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T
     site_of<G>(g, s, x);
     const int64_t Vp = g.Vp;
     A f = semi_f1<G, T, d>(Uc, Ut_in, g, x, c);
-    A e, f2, eo;
-    load_alg_own(e, E, d, s, Vp);
-    load_alg_own(f2, F2, d, s, Vp);
+    A e, eo;
+    load_alg_own(e, Ebase, d, s, Vp);
     load_alg_own(eo, Et, d, s, Vp);
     const typename G::Real dt = (typename G::Real)c.dt;
 #pragma unroll
-    for (int k = 0; k < G::NG; ++k) e.c[k] += dt * (f.c[k] + f2.c[k]);
-    if constexpr (HOP && d == 2) {
-      A j;
-      load_alg_own(j, J, 0, s, Vp);
-#pragma unroll
-      for (int k = 0; k < G::NG; ++k) e.c[k] += j.c[k];
-    }
+    for (int k = 0; k < G::NG; ++k) e.c[k] = fmx(dt, f.c[k], e.c[k]);
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < G::NG; ++k) {
@@ -359,20 +352,41 @@ __device__ __forceinline__ void semi_iter_body(const T* __restrict__ Uc, const T
 // without the bound); the longitudinal link's terms need more registers than that allows.
 template <typename G, typename T, int d>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_semi_iter_t(const T* __restrict__ Uc, const T* __restrict__ Ut_in, const T* __restrict__ E,
-              const T* __restrict__ F2, const T* __restrict__ J, T* __restrict__ Et, T* __restrict__ Ut_out,
-              double* __restrict__ conv, const double* __restrict__ conv_prev, double tol, Geom g, StepConst c,
-              double omega) {
-  semi_iter_body<G, T, false, d>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
+k_semi_iter_t(const T* __restrict__ Uc, const T* __restrict__ Ut_in, const T* __restrict__ Ebase,
+              T* __restrict__ Et, T* __restrict__ Ut_out, double* __restrict__ conv,
+              const double* __restrict__ conv_prev, double tol, Geom g, StepConst c, double omega) {
+  semi_iter_body<G, T, d>(Uc, Ut_in, Ebase, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
 }
-template <typename G, typename T, bool HOP>
+template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_semi_iter_z(const T* __restrict__ Uc, const T* __restrict__ Ut_in,
-                                                     const T* __restrict__ E, const T* __restrict__ F2,
-                                                     const T* __restrict__ J, T* __restrict__ Et,
+                                                     const T* __restrict__ Ebase, T* __restrict__ Et,
                                                      T* __restrict__ Ut_out, double* __restrict__ conv,
                                                      const double* __restrict__ conv_prev, double tol, Geom g,
                                                      StepConst c, double omega) {
-  semi_iter_body<G, T, HOP, 2>(Uc, Ut_in, E, F2, J, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
+  semi_iter_body<G, T, 2>(Uc, Ut_in, Ebase, Et, Ut_out, conv, conv_prev, tol, g, c, omega);
+}
+
+// Ebase = E(t - dt/2) + dt F2 + [z] dt j, in place over F2 (F2 = f1(U(t), U(t - dt)); J holds
+// dt j_z on hop steps, else null): the part of the fixed-point map that does not change.
+template <typename G, typename T>
+__global__ void __launch_bounds__(256) k_semi_base(const T* __restrict__ E, T* __restrict__ F2,
+                                                   const T* __restrict__ J, Geom g, double dt) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)g.V) return;
+  const int d = blockIdx.y;
+  typename G::Alg e, f;
+  load_alg_own(e, E, d, s, g.Vp);
+  load_alg_own(f, F2, d, s, g.Vp);
+  const typename G::Real k = (typename G::Real)dt;
+#pragma unroll
+  for (int q = 0; q < G::NG; ++q) e.c[q] = fmx(k, f.c[q], e.c[q]);
+  if (J && d == 2) {
+    typename G::Alg j;
+    load_alg_own(j, J, 0, s, g.Vp);
+#pragma unroll
+    for (int q = 0; q < G::NG; ++q) e.c[q] += j.c[q];
+  }
+  store_alg(e, F2, d, s, g.Vp);
 }
 
 template <typename G, typename T>
@@ -382,12 +396,25 @@ __global__ void k_copy_alg(const T* __restrict__ src, T* __restrict__ dst, int64
 }
 
 template <typename G, typename T>
-void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st) {
+void launch_semi_f1(const T* Uc, const T* Uo, T* out, const Geom& g, const StepConst& c, hipStream_t st, T* cache) {
+  if (march_geometry(g)) {
+    MarchIter it{};
+    it.F = out;
+    it.cache = cache;
+    launch_semi_march<G, T>(Uc, Uo, g, c, 0, it, st);
+    return;
+  }
   const int bs = 256;
   const dim3 grid((unsigned)((g.V + bs - 1) / bs));
   hipLaunchKernelGGL((k_semi_f1<G, T, 0>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
   hipLaunchKernelGGL((k_semi_f1<G, T, 1>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
   hipLaunchKernelGGL((k_semi_f1<G, T, 2>), grid, dim3(bs), 0, st, Uc, Uo, out, g, c);
+}
+
+template <typename G, typename T>
+void launch_semi_base(const T* E, T* F2, const T* J, const Geom& g, double dt, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL((k_semi_base<G, T>), dim3((unsigned)((g.V + bs - 1) / bs), 3), dim3(bs), 0, st, E, F2, J, g, dt);
 }
 
 template <typename G, typename T>
@@ -418,9 +445,9 @@ void launch_zero(double* p, int n, hipStream_t st) {
 }
 
 template <typename G, typename T>
-void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, const T* J, T* Et, T* Ut_out,
-                      double* conv, const double* conv_prev, double tol, const Geom& g, const StepConst& c,
-                      hipStream_t st) {
+void launch_semi_iter(const T* Uc, const T* Ut_in, const T* Ebase, T* Et, T* Ut_out, double* conv,
+                      const double* conv_prev, double tol, const Geom& g, const StepConst& c, hipStream_t st,
+                      const T* cache) {
   const int bs = 256;
   // Under-relaxation of the fixed-point map E -> E(t-dt/2) + dt (F2 + f1(U, U(E)) + j).  Its
   // linearisation is implicit only in the slice-averaged transverse terms, with eigenvalues in
@@ -428,18 +455,27 @@ void launch_semi_iter(const T* Uc, const T* Ut_in, const T* E, const T* F2, cons
   // omega = 2 / (2 - lambda_min) = 1 / (1 + 2 dt^2 / a_T^2) minimises the spectral radius of
   // the relaxed map (0.25 -> 0.11 at dt = a_L, a_T = 4 a_L).  Same fixed point.
   const double omega = 1.0 / (1.0 + 2.0 * c.dt * c.dt / (c.a[0] * c.a[0]));
+  if (march_geometry(g)) {
+    MarchIter it{};
+    it.Ebase = Ebase;
+    it.Et = Et;
+    it.Ut_out = Ut_out;
+    it.conv = conv;
+    it.conv_prev = conv_prev;
+    it.tol = tol;
+    it.omega = omega;
+    it.cache = (void*)cache;
+    launch_semi_march<G, T>(Uc, Ut_in, g, c, 1, it, st);
+    return;
+  }
   const dim3 grid((unsigned)((g.V + bs - 1) / bs));
   // one launch per direction: a kernel holds only that direction's terms
-  hipLaunchKernelGGL((k_semi_iter_t<G, T, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
-                     conv_prev, tol, g, c, omega);
-  hipLaunchKernelGGL((k_semi_iter_t<G, T, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
-                     conv_prev, tol, g, c, omega);
-  if (c.hop)
-    hipLaunchKernelGGL((k_semi_iter_z<G, T, true>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
-                       conv_prev, tol, g, c, omega);
-  else
-    hipLaunchKernelGGL((k_semi_iter_z<G, T, false>), grid, dim3(bs), 0, st, Uc, Ut_in, E, F2, J, Et, Ut_out, conv,
-                       conv_prev, tol, g, c, omega);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 0>), grid, dim3(bs), 0, st, Uc, Ut_in, Ebase, Et, Ut_out, conv, conv_prev,
+                     tol, g, c, omega);
+  hipLaunchKernelGGL((k_semi_iter_t<G, T, 1>), grid, dim3(bs), 0, st, Uc, Ut_in, Ebase, Et, Ut_out, conv, conv_prev,
+                     tol, g, c, omega);
+  hipLaunchKernelGGL((k_semi_iter_z<G, T>), grid, dim3(bs), 0, st, Uc, Ut_in, Ebase, Et, Ut_out, conv, conv_prev, tol,
+                     g, c, omega);
 }
 
 template <typename G, typename T>
@@ -449,14 +485,15 @@ void launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 }
 
 #define GL_SEMI_INST(G, T)                                                                                      \
-  template void launch_semi_f1<G, T>(const T*, const T*, T*, const Geom&, const StepConst&, hipStream_t);      \
+  template void launch_semi_f1<G, T>(const T*, const T*, T*, const Geom&, const StepConst&, hipStream_t, T*); \
   template void launch_semi_keep<G, T>(const T*, const T*, T*, const Geom&, hipStream_t);                    \
   template void launch_semi_begin<G, T>(const T*, const T*, const T*, const T*, T*, T*, T*, const Geom&,        \
                                         const StepConst&, \
                                         hipStream_t);                                                          \
   template void launch_semi_hop<G, T>(const T*, T*, T*, T*, bool, const Geom&, const StepConst&, hipStream_t); \
-  template void launch_semi_iter<G, T>(const T*, const T*, const T*, const T*, const T*, T*, T*, double*,      \
-                                       const double*, double, const Geom&, const StepConst&, hipStream_t);     \
+  template void launch_semi_iter<G, T>(const T*, const T*, const T*, T*, T*, double*, const double*, double,    \
+                                       const Geom&, const StepConst&, hipStream_t, const T*);                  \
+  template void launch_semi_base<G, T>(const T*, T*, const T*, const Geom&, double, hipStream_t);             \
   template void launch_copy<G, T>(const T*, T*, int64_t, hipStream_t);
 GL_SEMI_INST(Su2<double>, double)
 GL_SEMI_INST(Su3<double>, double)
