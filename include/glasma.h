@@ -202,6 +202,19 @@ int glasma_deposit_current(glasma_ctx* ctx, void* j_out);
  * state.  Asynchronous for the leapfrog. */
 int glasma_observe(glasma_ctx* ctx, double* d_out);
 
+/* glasma_observe for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same observables,
+ * bitwise, with the per-block partial sums held in a file-scope device array of the library
+ * (4 MiB per GPU the library runs on, kept until the process ends) instead of the context's
+ * work buffer.  The call allocates and frees nothing (no hipMalloc, no library routine that
+ * allocates); the first call on a device looks the array's address up for it.  Every call
+ * on one GPU shares that array and each call writes every partial it reads, so nothing
+ * needs clearing; calls that overlap on one GPU (several streams or host threads) race.
+ * Limits: the leapfrog scheme (scheme 1: GLASMA_E_ARG), and lattices whose partial sums
+ * (nz ceil(nt^2 / 256) work-groups x 9 doubles) fit in the array, up to 524288 doubles
+ * (512 x 64 x 64 needs 73728; larger: GLASMA_E_ARG with the sizes).  Asynchronous. */
+int glasma_observe_noalloc(glasma_ctx* ctx, double* d_out);
+
 /* n >= 1 steps, writing to d_out (device, as glasma_observe) the observables of the state
  * the last step starts from: the same as glasma_step(n - 1), glasma_observe,
  * glasma_step(1), up to rounding.  For the FP64 leapfrog with nt a multiple of 64 the last

@@ -65,6 +65,7 @@ def _load():
         "glasma_step": ([P, I32], C.c_int),
         "glasma_deposit_current": ([P, V], C.c_int),
         "glasma_observe": ([P, V], C.c_int),
+        "glasma_observe_noalloc": ([P, V], C.c_int),
         "glasma_rest_frame": ([P, V, V], C.c_int),
         "glasma_step_observe": ([P, I32, V], C.c_int),
         "glasma_observables": ([P, D, D, D, D, D], C.c_int),

@@ -34,6 +34,7 @@ struct glasma_ctx {
   int32_t adj_steps, adj_every;
   int adj_off0;
   const void* adj_work;
+  int device;         // HIP device current when the context was created
   std::string err;
 };
 
@@ -204,6 +205,8 @@ int glasma_create(const glasma_params* p, const glasma_buffers* b, void* stream,
   c->ready = false;
   c->last_iters = 0;
   c->adj_ok = false;
+  c->device = 0;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   *out = c;
   return GLASMA_OK;
 }
@@ -565,6 +568,18 @@ int glasma_deposit_current(glasma_ctx* c, void* j_out) {
   return GLASMA_OK;
 }
 
+// Observables of the leapfrog state with the per-block partial sums in `partial`
+// (observe_partial_doubles doubles of device memory).
+static int observe_leapfrog(glasma_ctx* c, const StepConst& sc, double* partial, double* d_out) {
+  dispatch(c, [&]<typename G, typename T>() -> int {
+    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, (const T*)nullptr, c->g, sc, partial,
+                         d_out, c->stream);
+    return 0;
+  });
+  HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
 int glasma_observe(glasma_ctx* c, double* d_out) {
   if (!c || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
   if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
@@ -578,14 +593,23 @@ int glasma_observe(glasma_ctx* c, double* d_out) {
     if (rc) return rc;
     return semi_observe_solved(c, sc, d_out);
   }
-  double* partial = (double*)c->b.work;
-  dispatch(c, [&]<typename G, typename T>() -> int {
-    launch_observe<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, (const T*)nullptr, c->g, sc, partial,
-                         d_out, c->stream);
-    return 0;
-  });
-  HIPCHK(c, hipGetLastError());
-  return GLASMA_OK;
+  return observe_leapfrog(c, sc, (double*)c->b.work, d_out);
+}
+
+int glasma_observe_noalloc(glasma_ctx* c, double* d_out) {
+  if (!c || !d_out) return fail(c, GLASMA_E_ARG, "NULL argument");
+  if (!c->ready) return fail(c, GLASMA_E_STATE, "no state");
+  if (c->p.scheme != 0)
+    return fail(c, GLASMA_E_ARG, "glasma_observe_noalloc covers the leapfrog scheme (the semi-implicit observables "
+                                 "need the solve of the next step)");
+  double* scratch = nullptr;
+  size_t cap = 0;
+  HIPCHK(c, observe_static_scratch(c->device, &scratch, &cap));
+  if (observe_partial_doubles(c->g) > cap)
+    return fail(c, GLASMA_E_ARG, "lattice too large for glasma_observe_noalloc: its partial sums need " +
+                                     std::to_string(observe_partial_doubles(c->g)) + " doubles, the static scratch "
+                                     "holds " + std::to_string(cap) + " (use glasma_observe)");
+  return observe_leapfrog(c, step_const(c), scratch, d_out);
 }
 
 int glasma_rest_frame(glasma_ctx* c, const double* d_obs, double* d_out) {

@@ -48,6 +48,9 @@ template <typename G, typename T>
 void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const T* En, const Geom& g,
                     const StepConst& c, double* partial, double* out, hipStream_t st);
 size_t observe_partial_doubles(const Geom& g);
+// address (for `device`) and size in doubles of the file-scope partial-sum array used by the
+// allocation-free observables call
+hipError_t observe_static_scratch(int device, double** ptr, size_t* capacity);
 // Observing step (FP64 leapfrog, nt a multiple of 64): the Gauss residual kernel runs on
 // the state before the step, the step kernel adds the energy slots, then the finish pass.
 bool fused_observe_geometry(const Geom& g);

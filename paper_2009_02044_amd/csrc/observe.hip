@@ -14,6 +14,7 @@
 // link unitarity and a non-finite count.  A block covers part of one z layer; its
 // partial sums land in a fixed slot and a single-block pass adds them in a fixed
 // order, so results are bitwise reproducible.
+#include <mutex>
 #include "internal.h"
 #include "stencil.h"
 #include "reduce.h"
@@ -282,6 +283,38 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
     hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c,
                        partial);
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
+}
+
+// ---- partial sums of the allocation-free observables call -------------------------
+// A file-scope device array, one per GPU the library runs on (held until the process ends),
+// for callers that cannot allocate; host code uses it only through the address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+constexpr size_t OBS_STATIC_DOUBLES = (size_t)1 << 19;   // 4 MiB
+static __device__ __align__(256) double g_obs_static[OBS_STATIC_DOUBLES];
+constexpr int OBS_STATIC_MAX_DEVICES = 64;
+static double* g_obs_static_ptr[OBS_STATIC_MAX_DEVICES];
+static std::mutex g_obs_static_mu;
+
+hipError_t observe_static_scratch(int device, double** ptr, size_t* capacity) {
+  *capacity = OBS_STATIC_DOUBLES;
+  if (device < 0 || device >= OBS_STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_obs_static_mu);
+  if (!g_obs_static_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_obs_static));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_obs_static_ptr[device] = (double*)p;
+  }
+  *ptr = g_obs_static_ptr[device];
+  return hipSuccess;
 }
 
 // ---- pieces of the observing step (nt a multiple of 64: full column-map blocks) ----

@@ -124,6 +124,11 @@ class Lattice:
         """Asynchronous: write slices + scalars into the float64 device tensor `out`."""
         self._chk(lib.glasma_observe(self.ctx, C.c_void_p(out.data_ptr())))
 
+    def observe_noalloc(self, out):
+        """As observe(), with the partial sums in the library's static device array
+        (glasma_observe_noalloc: allocates nothing; leapfrog; lattices up to its limit)."""
+        self._chk(lib.glasma_observe_noalloc(self.ctx, C.c_void_p(out.data_ptr())))
+
     def step_observe(self, n, out):
         """n >= 1 steps; `out` (an obs_buffer()) receives the observables of the state the
         last step starts from (glasma_step_observe).  Asynchronous."""
