@@ -307,6 +307,18 @@ int glasma_adjoint_backward(glasma_ctx* ctx, int32_t z0, int32_t z1, double scal
                             const double* baseA, const double* baseB, double* L, double* dE0, double* drhoA0,
                             double* drhoB0, double* dampA, double* dampB);
 
+/* Reverse pass for a general loss of the final state, given its cotangent: lamU [3][n_g][V]
+ * = dL/d eps^a for the left variation U_i(x) -> exp(i eps^a t^a) U_i(x) of the final links,
+ * ebarE [3][n_g][V] = dL/dE^a of the final E(t - dt/2), rbarA, rbarB [n_g][V] = dL/drho^a
+ * of the final charges at their physical positions (device double arrays; NULL = zero).
+ * The slab energy of glasma_adjoint_backward is one such cotangent.  Outputs as there,
+ * plus dU0 [3][n_g][V] (may be NULL): the same left-variation derivative for the starting
+ * links.  Requirements and errors as glasma_adjoint_backward.  Asynchronous. */
+int glasma_adjoint_backward_cotangent(glasma_ctx* ctx, void* work, size_t work_bytes, const double* lamU,
+                                      const double* ebarE, const double* rbarA, const double* rbarB,
+                                      const double* baseA, const double* baseB, double* dU0, double* dE0,
+                                      double* drhoA0, double* drhoB0, double* dampA, double* dampB);
+
 /* The loss L above at the current state (host result).  Uses the context's work buffer.
  * Synchronous. */
 int glasma_slab_energy(glasma_ctx* ctx, int32_t z0, int32_t z1, double* L);

@@ -80,6 +80,7 @@ def _load():
         "glasma_adjoint_forward": ([P, I32, I32, V, C.c_size_t], C.c_int),
         "glasma_adjoint_backward": ([P, I32, I32, C.c_double, V, C.c_size_t, V, V, D, V, V, V, V, V], C.c_int),
         "glasma_slab_energy": ([P, I32, I32, D], C.c_int),
+        "glasma_adjoint_backward_cotangent": ([P, V, C.c_size_t, V, V, V, V, V, V, V, V, V, V, V, V], C.c_int),
         "glasma_batch_layout": ([C.POINTER(Params), I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(C.c_size_t)], C.c_int),
         "glasma_batch_create": ([C.POINTER(Params), I32, C.POINTER(I32), C.POINTER(I32), V, V, C.POINTER(P)], C.c_int),
         "glasma_batch_destroy": ([P], C.c_int),

@@ -1246,13 +1246,16 @@ int glasma_adjoint_forward(glasma_ctx* c, int32_t steps, int32_t ckpt_every, voi
   return GLASMA_OK;
 }
 
-int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale, void* work, size_t work_bytes,
-                            const double* baseA, const double* baseB, double* L, double* dE0, double* drhoA0,
-                            double* drhoB0, double* dampA, double* dampB) {
-  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+// The reverse pass of the last glasma_adjoint_forward: seed(...) writes the cotangent of the
+// final state into lam, ebar, rbarA, rbarB (plain double arrays in the work buffer), then
+// every segment is recomputed from its checkpoint and reversed step by step; the
+// cotangents of the starting state are copied out.
+template <class Seed>
+static int adjoint_reverse(glasma_ctx* c, void* work, size_t work_bytes, Seed&& seed, const double* baseA,
+                           const double* baseB, double* dU0, double* dE0, double* drhoA0, double* drhoB0,
+                           double* dampA, double* dampB) {
   if (!c->adj_ok || work != c->adj_work || c->step != c->adj_s0 + c->adj_steps)
     return fail(c, GLASMA_E_STATE, "glasma_adjoint_forward with this work buffer must come right before");
-  if (z0 < 0 || z1 > c->g.nz || z0 >= z1) return fail(c, GLASMA_E_ARG, "need 0 <= z0 < z1 <= nz");
   const int32_t steps = c->adj_steps, every = c->adj_every;
   const AdjRegion a = adj_region(&c->p, steps, every);
   if (work_bytes < a.end) return fail(c, GLASMA_E_ARG, "work buffer smaller than glasma_adjoint_layout");
@@ -1263,7 +1266,6 @@ int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale,
   double* rB[2] = {(double*)(w + a.rB0), (double*)(w + a.rB1)};
   double* K = (double*)(w + a.K);
   double* part = (double*)(w + a.part);
-  double* Lout = part + adj_loss_partials(c->g);
   const double sp[3] = {c->p.a_T, c->p.a_T, c->p.a_L};
   const int64_t s0 = c->adj_s0;
   const int off0 = c->adj_off0;
@@ -1271,8 +1273,8 @@ int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale,
   int cur = 0;
   int rc = dispatch(c, [&]<typename G, typename T>() -> int {
     const StatePtr fin = ckpt(a.nseg);
-    launch_adj_loss<G, T>((const T*)fin.U, (const T*)fin.E, c->g, sp, z0, z1, scale, lam, ebar, rA[0], rB[0], part,
-                          Lout, c->stream);
+    int r = seed.template operator()<G, T>(fin, lam, ebar, rA[0], rB[0], part);
+    if (r) return r;
     const size_t nE = 3 * (size_t)c->ng * c->g.Vp * sizeof(T), nR = (size_t)c->ng * c->g.Vp * sizeof(T);
     for (int64_t k = a.nseg - 1; k >= 0; --k) {
       const int64_t sk = s0 + k * every;
@@ -1308,6 +1310,7 @@ int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale,
       }
     }
     const size_t n3 = 3 * (size_t)c->ng * c->g.V * sizeof(double), n1 = (size_t)c->ng * c->g.V * sizeof(double);
+    if (dU0) HIPCHK(c, hipMemcpyAsync(dU0, lam, n3, hipMemcpyDeviceToDevice, c->stream));
     if (dE0) HIPCHK(c, hipMemcpyAsync(dE0, ebar, n3, hipMemcpyDeviceToDevice, c->stream));
     if (drhoA0) HIPCHK(c, hipMemcpyAsync(drhoA0, rA[cur], n1, hipMemcpyDeviceToDevice, c->stream));
     if (drhoB0) HIPCHK(c, hipMemcpyAsync(drhoB0, rB[cur], n1, hipMemcpyDeviceToDevice, c->stream));
@@ -1318,11 +1321,52 @@ int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale,
   });
   if (rc) return rc;
   HIPCHK(c, hipGetLastError());
+  return GLASMA_OK;
+}
+
+int glasma_adjoint_backward(glasma_ctx* c, int32_t z0, int32_t z1, double scale, void* work, size_t work_bytes,
+                            const double* baseA, const double* baseB, double* L, double* dE0, double* drhoA0,
+                            double* drhoB0, double* dampA, double* dampB) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  if (z0 < 0 || z1 > c->g.nz || z0 >= z1) return fail(c, GLASMA_E_ARG, "need 0 <= z0 < z1 <= nz");
+  const double sp[3] = {c->p.a_T, c->p.a_T, c->p.a_L};
+  double* Lout = nullptr;
+  // the slab energy's own cotangent as the seed
+  auto seed = [&]<typename G, typename T>(const StatePtr& fin, double* lam, double* ebar, double* rA, double* rB,
+                                          double* part) -> int {
+    Lout = part + adj_loss_partials(c->g);
+    launch_adj_loss<G, T>((const T*)fin.U, (const T*)fin.E, c->g, sp, z0, z1, scale, lam, ebar, rA, rB, part, Lout,
+                          c->stream);
+    return GLASMA_OK;
+  };
+  int rc = adjoint_reverse(c, work, work_bytes, seed, baseA, baseB, nullptr, dE0, drhoA0, drhoB0, dampA, dampB);
+  if (rc) return rc;
   if (L) {
     HIPCHK(c, hipMemcpyAsync(L, Lout, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return GLASMA_OK;
+}
+
+int glasma_adjoint_backward_cotangent(glasma_ctx* c, void* work, size_t work_bytes, const double* lamU,
+                                      const double* ebarE, const double* rbarA, const double* rbarB,
+                                      const double* baseA, const double* baseB, double* dU0, double* dE0,
+                                      double* drhoA0, double* drhoB0, double* dampA, double* dampB) {
+  if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
+  const size_t n3 = 3 * (size_t)c->ng * c->g.V, n1 = (size_t)c->ng * c->g.V;
+  auto seed = [&]<typename G, typename T>(const StatePtr&, double* lam, double* ebar, double* rA, double* rB,
+                                          double*) -> int {
+    auto put = [&](double* dst, const double* src, size_t n) -> int {
+      if (src) HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      else launch_zero(dst, (int)n, c->stream);
+      return GLASMA_OK;
+    };
+    int r;
+    if ((r = put(lam, lamU, n3)) || (r = put(ebar, ebarE, n3)) || (r = put(rA, rbarA, n1)) || (r = put(rB, rbarB, n1)))
+      return r;
+    return GLASMA_OK;
+  };
+  return adjoint_reverse(c, work, work_bytes, seed, baseA, baseB, dU0, dE0, drhoA0, drhoB0, dampA, dampB);
 }
 
 int glasma_slab_energy(glasma_ctx* c, int32_t z0, int32_t z1, double* L) {

@@ -205,6 +205,23 @@ class Lattice:
         out["L"] = L.value
         return out
 
+    def adjoint_backward_cotangent(self, work, lamU=None, ebarE=None, rbarA=None, rbarB=None, baseA=None,
+                                   baseB=None):
+        """Gradients of a general loss of the final state of the last adjoint_forward, given
+        its cotangent (device float64 tensors, None = 0): lamU, ebarE (3, n_g, V); rbarA,
+        rbarB (n_g, V).  Returns dU0, dE0 (3, n_g, V), drhoA0, drhoB0 (n_g, V), dampA, dampB (V,)."""
+        f = dict(dtype=torch.float64, device=self.device)
+        out = {"dU0": torch.empty(3, self.ng, self.V, **f), "dE0": torch.empty(3, self.ng, self.V, **f),
+               "drhoA0": torch.empty(self.ng, self.V, **f), "drhoB0": torch.empty(self.ng, self.V, **f),
+               "dampA": torch.empty(self.V, **f), "dampB": torch.empty(self.V, **f)}
+        self._chk(lib.glasma_adjoint_backward_cotangent(
+            self.ctx, C.c_void_p(work.data_ptr()), work.numel(),
+            self._dev(lamU, (3, self.ng, self.V), "lamU"), self._dev(ebarE, (3, self.ng, self.V), "ebarE"),
+            self._dev(rbarA, (self.ng, self.V), "rbarA"), self._dev(rbarB, (self.ng, self.V), "rbarB"),
+            self._dev(baseA, (self.ng, self.V), "baseA"), self._dev(baseB, (self.ng, self.V), "baseB"),
+            *[C.c_void_p(out[k].data_ptr()) for k in ("dU0", "dE0", "drhoA0", "drhoB0", "dampA", "dampB")]))
+        return out
+
     @staticmethod
     def unpack_obs(buf, nz):
         h = buf.detach().cpu().numpy()

@@ -291,3 +291,82 @@ def test_full_workload_fp32_forward_gradient_against_fp64_forward():
     say("relative 2-norm differences FP32 vs FP64 forward", out, "L", g32["L"], g64["L"])
     assert abs(g32["L"] - g64["L"]) < 1e-4 * abs(g64["L"])
     assert max(out.values()) < 2e-4, out
+
+
+def _final_tangent(st, tan, steps):
+    for _ in range(steps):
+        st, tan = adjoint.tangent_step(st, tan)
+    return st, tan
+
+
+def _comp_of(X, nc, lead):
+    """oracle matrices (lead..., nz, ny, nx, N, N) -> C-ABI components (lead..., n_g, V)."""
+    from oracle import su
+    c = su.to_components(X)                       # (lead..., nz, ny, nx, n_g)
+    ng = c.shape[-1]
+    c = c.reshape(lead + (-1, ng))
+    return np.ascontiguousarray(np.swapaxes(c, -1, -2))
+
+
+@pytest.mark.parametrize("nc", [2, 3])
+def test_general_cotangent_against_oracle_jvp(nc):
+    """glasma_adjoint_backward_cotangent: for a random cotangent c of the final state (links,
+    E, both charge populations) and random directions v of the starting state (links, E,
+    charges), <J^T c, v> from the GPU's reverse pass equals <c, J v> with J v the oracle's
+    tangent-linear propagation (nz = 12, nt = 4, 7 steps in checkpoint segments 3, 3, 1 with
+    hops); and for a second observable, L2 = sum_x w(x) |E_z(x)|^2 of the final state
+    (cotangent 2 w E_z), its gradient along v equals the oracle's JVP of L2.  FP64, 1e-10."""
+    import torch
+    pkg = lattice_or_skip()
+    nz, nt, steps, every = 12, 4, 7, 3
+    say(f"case: general cotangent nc={nc}")
+    st = small_state(nc, nz, nt, seed=700 + nc)
+    ng, V = nc * nc - 1, nz * nt * nt
+    lat = pkg.Lattice(nc=nc, nz=nz, nt=nt, a_T=4.0, a_L=1.0, dt=0.5, fp=64)
+    lat.init_state(*to_comp(st), step0=st.step)
+    work = lat.adjoint_work(steps, every)
+    lat.adjoint_forward(steps, every, work)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=lat.device)
+    cU = synth.normal(710, (3, ng, V), 1.0)
+    cE = synth.normal(711, (3, ng, V), 1.0)
+    cA = synth.normal(712, (ng, V), 1.0)
+    cB = synth.normal(713, (ng, V), 1.0)
+    g = lat.adjoint_backward_cotangent(work, dev(cU), dev(cE), dev(cA), dev(cB))
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    worst = 0.0
+    for k in range(4):
+        vU = synth.normal(720 + k, (3, ng, V), 1.0)
+        vE = synth.normal(730 + k, (3, ng, V), 1.0)
+        vA = synth.normal(740 + k, (ng, V), 1.0)
+        vB = synth.normal(750 + k, (ng, V), 1.0)
+        tan = adjoint.tangent_from_components(st, to_oracle_alg(vU, nz, nt, (3,)), to_oracle_alg(vE, nz, nt, (3,)),
+                                              to_oracle_alg(vA, nz, nt, ()), to_oracle_alg(vB, nz, nt, ()))
+        _, tf = _final_tangent(st, tan, steps)
+        rhs = (np.sum(cU * _comp_of(tf[0], nc, (3,))) + np.sum(cE * _comp_of(tf[1], nc, (3,)))
+               + np.sum(cA * _comp_of(tf[2], nc, ())) + np.sum(cB * _comp_of(tf[3], nc, ())))
+        lhs = np.sum(g["dU0"] * vU) + np.sum(g["dE0"] * vE) + np.sum(g["drhoA0"] * vA) + np.sum(g["drhoB0"] * vB)
+        err = abs(lhs - rhs) / abs(rhs)
+        worst = max(worst, err)
+        say(f"  direction {k}: <J^T c, v> {lhs:.12e}  <c, J v> {rhs:.12e}  rel {err:.1e}")
+        assert err < 1e-10
+    # a second observable: L2 = sum_x w(x) |E_z(x)|^2 of the final state
+    fin = lattice.evolve(st, steps)
+    Ez = _comp_of(fin.E, nc, (3,))[2]                      # (n_g, V)
+    wgt = synth.uniform(760, (V,), 0.0, 1.0)
+    cE2 = np.zeros((3, ng, V))
+    cE2[2] = 2.0 * wgt[None, :] * Ez
+    g2 = lat.adjoint_backward_cotangent(work, None, dev(cE2), None, None)
+    g2 = {k: v.cpu().numpy() for k, v in g2.items()}
+    vE = synth.normal(770, (3, ng, V), 1.0)
+    vA = synth.normal(771, (ng, V), 1.0)
+    tan = adjoint.tangent_from_components(st, None, to_oracle_alg(vE, nz, nt, (3,)), to_oracle_alg(vA, nz, nt, ()),
+                                          None)
+    fst, tf = _final_tangent(st, tan, steps)
+    from oracle import su
+    dEz = su.to_components(tf[1][2])                       # (nz, ny, nx, n_g)
+    Ezf = su.to_components(fst.E[2])
+    jvp = np.sum(2.0 * wgt.reshape(nz, nt, nt)[..., None] * Ezf * dEz)
+    lhs = np.sum(g2["dE0"] * vE) + np.sum(g2["drhoA0"] * vA)
+    say(f"  second observable: GPU {lhs:.12e} oracle JVP {jvp:.12e}")
+    assert abs(lhs - jvp) <= 1e-10 * abs(jvp)
+    assert np.all(g2["dU0"] == g2["dU0"])                  # finite output
