@@ -28,6 +28,23 @@ def _compile(src, objdir, extra):
     return obj
 
 
+PROBE_SRC = os.path.join(CSRC, "valu_probe.hip")
+PROBE_OUT = os.path.join(HERE, "valu_probe")
+
+
+def build_probe(verbose=False):
+    """The stand-alone issue-rate probe (an executable; not part of the library)."""
+    tmp = PROBE_OUT + ".tmp"
+    r = subprocess.run(["hipcc", *[f for f in FLAGS if f != "-fPIC"], PROBE_SRC, "-o", tmp],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{r.stderr}")
+    os.replace(tmp, PROBE_OUT)
+    if verbose:
+        print("built", PROBE_OUT)
+    return PROBE_OUT
+
+
 def build(verbose=False, extra_flags=(), out=None):
     """Compile every source and link the shared library (out: path of the .so)."""
     out = out or OUT
@@ -48,4 +65,5 @@ def build(verbose=False, extra_flags=(), out=None):
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_probe(verbose=True)
     sys.exit(0)
