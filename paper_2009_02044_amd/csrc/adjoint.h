@@ -38,8 +38,11 @@ template <typename A> GL_HD void axpy(A& y, double s, const A& x) {
 }
 
 // c int_0^1 exp(-i s c E) Lam exp(i s c E) ds for hermitian E, Lam (components): the series
-// sum_k (-ad_B)^k Lam / (k+1)!, B = i c E / 2^m with |ad_B| <= 1/2, then m doublings
-// I(2B) = (I(B) + e^-B I(B) e^B) / 2.  Truncation error below 2^-15 / 16! relative.
+// sum_k (-ad_B)^k Lam / (k+1)!, B = i c E / 2^m with |ad_B| <= rho <= 1/2, then m doublings
+// I(2B) = (I(B) + e^-B I(B) e^B) / 2.  The series stops after the fewest terms N whose
+// tail bound rho^(N+1) / (N+2)! is below 2^-15 / 16! (the bound of 14 terms at rho = 1/2),
+// so the truncation error is below 2^-15 / 16! relative for every field; small fields
+// (rho ~ 0.02-0.1) need 7-10 terms.
 template <typename G>
 GL_HD typename G::Alg dexp_transpose(const typename G::Alg& e, double c, const typename G::Alg& lam) {
   using L = typename G::Link;
@@ -56,9 +59,17 @@ GL_HD typename G::Alg dexp_transpose(const typename G::Alg& e, double c, const t
   for (int k = 0; k < NG; ++k) be.c[k] = c * sc * e.c[k];
   const L B = AdjOps<G>::anti(be);
   const L lh = AdjOps<G>::anti(lam);
+  const double rho = 2.0 * r * sc;                             // bound on |ad_B|
+  const double tail_max = 3.0517578125e-05 / 20922789888000.0;   // 2^-15 / 16!
+  int nt = 1;
+  double tail = rho * rho / 6.0;                               // rho^(N+1) / (N+2)! at N = 1
+  while (nt < 14 && tail > tail_max) {
+    ++nt;
+    tail *= rho / (double)(nt + 2);
+  }
   L T = lh;
 #pragma unroll 1
-  for (int k = 14; k >= 1; --k) {
+  for (int k = nt; k >= 1; --k) {
     const L ad = commut<G>(B, T);
     T = lh;
     G::add_to(T, ad, -1.0 / (double)(k + 1));

@@ -128,7 +128,10 @@ def test_device_exp_derivative_transpose_matches_expm_frechet(nc):
     from paper_2009_02044_amd import host_group_op
     ng = nc * nc - 1
     t = su.generators(nc)
-    cases = [(0.3, 0.5), (2.0, 1.0), (4.0, 2.5), (1.0, 0.0), (0.5, 1e-5)]
+    # norms from zero through the range where the series shortens (7-13 terms) to the
+    # doubling range, where it keeps all 14
+    cases = [(0.3, 0.5), (2.0, 1.0), (4.0, 2.5), (1.0, 0.0), (0.5, 1e-5), (2.0, 0.004), (0.5, 0.05),
+             (2.0, 0.02), (2.0, 0.05), (0.5, 0.4)]
     for k, (c, amp) in enumerate(cases):
         X = synth.normal(30 + k, (ng,), amp)
         Lm = synth.normal(40 + k, (ng,), 1.0)
