@@ -425,6 +425,25 @@ def run_precision(w, steps, every=256):
             "fp64_wall_s": series[64]["wall_s"], "fp32_wall_s": series[32]["wall_s"], "rows": rows}
 
 
+def memory_ceiling(nbytes=1 << 30, reps=10):
+    """What the memory system delivers on this device, as a ceiling for the HBM fractions: a
+    device-to-device copy of 1 GiB (torch's copy kernel; read + write bytes), HIP events on the
+    current stream, best of reps."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        ev0.record()
+        y.copy_(x)
+        ev1.record()
+        torch.cuda.synchronize()
+        best = min(best, ev0.elapsed_time(ev1))
+    del x, y
+    return {"copy_GBps": 2 * nbytes / (best * 1e-3) / 1e9, "bytes": nbytes}
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload: a 64-layer slab of the
     beam axis at the full transverse size, stepped until ~budget_s of CPU time."""
@@ -599,6 +618,9 @@ def main():
     bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
     launch_bytes = bpsu * w.sites
     achieved = launch_bytes / (r64["kernel_ms"] * 1e-3) / 1e9
+    ceil = memory_ceiling()
+    print(f"[bench] memory ceiling: device copy {ceil['copy_GBps']:.0f} GB/s",
+          file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w)
@@ -625,7 +647,9 @@ def main():
                      "kernel_site_updates_per_s": w.sites / (r64["kernel_ms"] * 1e-3),
                      "bytes_per_site_update": bpsu,
                      "bytes_row": "SU(3) FP64, links stored by 2 rows (12 reals): 2(288 + 192) + 128 x dt/a_L",
-                     "bytes_per_launch": launch_bytes},
+                     "bytes_per_launch": launch_bytes,
+                     "copy_ceiling_GBps": ceil["copy_GBps"],
+                     "frac_of_copy_ceiling": achieved / ceil["copy_GBps"]},
         "checks": {"gauss_rel": r64["gauss_rel"], "unitarity": r64["unitarity"]},
         "forms": forms,
         "cpu_baseline": cpu,

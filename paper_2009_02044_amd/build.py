@@ -28,21 +28,25 @@ def _compile(src, objdir, extra):
     return obj
 
 
-PROBE_SRC = os.path.join(CSRC, "valu_probe.hip")
-PROBE_OUT = os.path.join(HERE, "valu_probe")
+PROBES = ["valu_probe", "hbm_probe"]
 
 
 def build_probe(verbose=False):
-    """The stand-alone issue-rate probe (an executable; not part of the library)."""
-    tmp = PROBE_OUT + ".tmp"
-    r = subprocess.run(["hipcc", *[f for f in FLAGS if f != "-fPIC"], PROBE_SRC, "-o", tmp],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{r.stderr}")
-    os.replace(tmp, PROBE_OUT)
-    if verbose:
-        print("built", PROBE_OUT)
-    return PROBE_OUT
+    """The stand-alone probes (executables, not part of the library): the VALU issue rate per
+    instruction form and the achievable memory bandwidth."""
+    outs = []
+    for name in PROBES:
+        out = os.path.join(HERE, name)
+        tmp = out + ".tmp"
+        r = subprocess.run(["hipcc", *[f for f in FLAGS if f != "-fPIC"], os.path.join(CSRC, name + ".hip"), "-o",
+                            tmp], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {name}.hip:\n{r.stderr}")
+        os.replace(tmp, out)
+        if verbose:
+            print("built", out)
+        outs.append(out)
+    return outs
 
 
 def build(verbose=False, extra_flags=(), out=None):
