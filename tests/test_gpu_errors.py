@@ -107,3 +107,34 @@ def test_non_finite_fields_are_reported(scheme):
     else:
         lat.step(2)
         assert code_of(lambda: lat.observables()) == E_NONFINITE
+
+
+def test_batch_observe_and_cotangent_errors():
+    """glasma_batch_observe refuses events without a state and an n_grid outside
+    [1, smallest N_z]; glasma_adjoint_backward_cotangent refuses a call without its forward
+    pass, a work buffer smaller than the layout and a context stepped since the forward pass.
+    Each context stays usable after the error."""
+    pkg = lattice_or_skip()
+    say("case: batch observe and cotangent reverse-pass errors")
+    shapes = [(16, 4), (24, 4)]
+    b = pkg.Batch(3, shapes, fp=64, reunit_every=0)
+    assert code_of(lambda: b.observe(8)) == E_STATE
+    for (nz, nt), lat in zip(shapes, b.events):
+        w, st = small_state(nz=nz, nt=nt)
+        lat.init_state(*to_comp(st), step0=0)
+    assert code_of(lambda: b.observe(0)) == E_ARG
+    assert code_of(lambda: b.observe(17)) == E_ARG          # above the smallest N_z
+    r = b.observe(16)
+    assert r["grid"].shape == (4, 16) and bool(r["grid"].isfinite().all())
+
+    lat = pkg.Lattice(nc=3, nz=8, nt=4, fp=64)
+    w, st = small_state()
+    lat.init_state(*to_comp(st), step0=0)
+    work = lat.adjoint_work(4, 2)
+    assert code_of(lambda: lat.adjoint_backward_cotangent(work)) == E_STATE   # no forward pass
+    lat.adjoint_forward(4, 2, work)
+    assert code_of(lambda: lat.adjoint_backward_cotangent(work[:256])) == E_ARG
+    g = lat.adjoint_backward_cotangent(work)                                  # zero cotangent
+    assert float(g["dE0"].abs().max()) == 0.0 and float(g["dU0"].abs().max()) == 0.0
+    lat.step(1)
+    assert code_of(lambda: lat.adjoint_backward_cotangent(work)) == E_STATE   # stepped since
