@@ -576,6 +576,18 @@ def main():
             detail[key] = rs
             print(f"[bench] semi-implicit dt={dt}: {rs['site_updates_per_s']:.3e} site-updates/s, "
                   f"{rs['iterations_mean']:.1f} iterations", file=sys.stderr, flush=True)
+        # the same run at dt = a_L in FP32 storage and arithmetic (fixed point iterated to 1e-6,
+        # about FP32 resolution); its final field energy against the FP64 run's
+        rs32 = run_plain(ws, 32, args.semi_steps, 1, obs_every=4, scheme=1, tol=1e-6)
+        key = "semi_implicit_fp32_dt1.0"
+        forms[key] = scalars(rs32, ("site_updates_per_s", "ms_per_step", "iterations_mean", "gauss_rel"))
+        forms[key]["tol"] = 1e-6
+        forms[key]["energy_rel_err_vs_fp64"] = abs(rs32["energy"] - detail["semi_implicit_fp64_dt1.0"]["energy"]) / abs(
+            detail["semi_implicit_fp64_dt1.0"]["energy"])
+        detail[key] = rs32
+        print(f"[bench] semi-implicit dt=1.0 fp32: {rs32['site_updates_per_s']:.3e} site-updates/s, "
+              f"{rs32['iterations_mean']:.1f} iterations, energy vs fp64 {forms[key]['energy_rel_err_vs_fp64']:.1e}",
+              file=sys.stderr, flush=True)
     if not args.no_adjoint:
         wa = synth.ADJOINT_SU3
         ra = run_adjoint(wa, wa.steps, 32)
