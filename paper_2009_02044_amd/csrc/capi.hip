@@ -251,7 +251,6 @@ int glasma_init_state(glasma_ctx* c, const double* U, const double* E, const dou
                       int64_t step0) {
   if (!c || !U || !E || !rhoA || !rhoB) return fail(c, GLASMA_E_ARG, "NULL argument");
   if (step0 < 0) return fail(c, GLASMA_E_ARG, "step0 must be >= 0");
-  const size_t V = c->g.V;
   int rc = dispatch(c, [&]<typename G, typename T>() -> int {
     int r;
     if ((r = upload<T>(c, c->b.U, U, 3, c->rs, c->r))) return r;
@@ -967,8 +966,8 @@ int glasma_batch_observe(glasma_batch* b, int32_t n_grid, double* class_avg, dou
 
 int glasma_batch_destroy(glasma_batch* b) {
   if (!b) return GLASMA_OK;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto* c : b->ev) glasma_destroy(c);
   delete b;
   return GLASMA_OK;
@@ -1059,8 +1058,8 @@ int glasma_batch_run(glasma_batch* b, int32_t steps, int32_t graph_chunk) {
   int32_t done = 0;
   if (graph_chunk > 0 && steps >= graph_chunk) {
     if (!b->exec || b->graph_steps != graph_chunk || b->graph_bs != b->bs || b->graph_grid != b->grid) {
-      if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-      if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+      if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
       BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
       for (int32_t k = 0; k < graph_chunk; ++k) batch_launch_one(b, bc, b->bs, b->grid);
       BHIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
@@ -1127,8 +1126,8 @@ int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t r
       first = false;
       if (ms < best) { best = ms; bb = bs; bg = gr; }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   b->bs = bb;
   b->grid = bg;
   char buf[160];
