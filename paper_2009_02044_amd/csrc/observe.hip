@@ -37,8 +37,10 @@ size_t observe_partial_doubles(const Geom& g) {
 // plaquettes are (f_x and f_y are complete there, see plaquette_forces), with
 // E(t + dt/2) = E(t - dt/2) - dt f_i / a_i (leapfrog) or read from En (semi-implicit);
 // the real traces (for B^2) are parked in LDS, trs[K OBS_BS + t], until the end.  Carrying
-// the projections and traces in registers held the pass at one wave per SIMD.
-template <typename G, typename T> struct PassObs {
+// the projections and traces in registers held the pass at one wave per SIMD.  HAS_EN is a
+// template parameter: a run-time choice between the two sources of E(t + dt/2) made the
+// compiler spill several hundred registers (a 3x slower pass).
+template <typename G, typename T, bool HAS_EN> struct PassObs {
   const T* E;
   const T* En;
   uint32_t s;
@@ -53,12 +55,14 @@ template <typename G, typename T> struct PassObs {
       constexpr int i = K - 1;
       typename G::Alg eo, enx;
       load_alg(eo, E, i, s, Vp);
-      if (En) load_alg(enx, En, i, s, Vp);
+      if constexpr (HAS_EN) load_alg(enx, En, i, s, Vp);
       const double ai = c.a[i];
       double d = 0.0;
 #pragma unroll
       for (int k = 0; k < G::NG; ++k) {
-        const double en = En ? (double)enx.c[k] : eo.c[k] - c.dt / ai * fi.c[k];
+        double en;
+        if constexpr (HAS_EN) en = (double)enx.c[k];
+        else en = eo.c[k] - c.dt / ai * fi.c[k];
         d += 0.5 * (eo.c[k] + en) * p.c[k];
       }
       sl += d / (c.a[2] * ai);
@@ -66,7 +70,7 @@ template <typename G, typename T> struct PassObs {
   }
 };
 
-template <typename G, typename T, bool XS>
+template <typename G, typename T, bool XS, bool HAS_EN>
 __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, const T* __restrict__ E,
                                                     const T* __restrict__ rhoA, const T* __restrict__ rhoB,
                                                     const T* __restrict__ En, Geom g, StepConst c,
@@ -95,7 +99,7 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
     // force terms of the E update, and the forward plaquettes, in double precision
     const OwnLinks<G, T, GL_OBS_OWN> own(fetch, s, slot, threadIdx.x, OBS_BS);
     A f[3];
-    PassObs<G, T> ob;
+    PassObs<G, T, HAS_EN> ob;
     ob.E = E;
     ob.En = En;
     ob.s = s;
@@ -111,7 +115,7 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
       const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
       A eo, en;
       load_alg(eo, E, i, s, Vp);
-      if (En) {
+      if constexpr (HAS_EN) {
         // semi-implicit scheme: E(t + dt/2) of the converged solve (the current included)
         load_alg(en, En, i, s, Vp);
       } else {
@@ -122,7 +126,7 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
       }
       L Ui;
       own(Ui, i);
-      if (c.hop && i == 2 && !En) {
+      if (!HAS_EN && c.hop && i == 2) {
         A rb, ra;
         load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
         load_alg(ra, rhoA, 0, site_index(g, x.x, x.y, slotA(wrap_add(z, 1, g.nz), c.offA, g.nz)), Vp);
@@ -276,12 +280,11 @@ void launch_observe(const T* U, const T* E, const T* rhoA, const T* rhoB, const 
   using Gd = typename GroupOf<G::NC, double>::type;
   const int nbx = obs_blocks_per_layer(g);
   // blocks start at multiples of 64 sites of a layer: rows lie in wavefronts when nt divides 64
-  if (rows_in_wavefronts(g.nt))
-    hipLaunchKernelGGL((k_observe<Gd, T, true>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c,
-                       partial);
-  else
-    hipLaunchKernelGGL((k_observe<Gd, T, false>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c,
-                       partial);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(nbx, g.nz), dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, En, g, c, partial);
+  };
+  if (rows_in_wavefronts(g.nt)) En ? go(k_observe<Gd, T, true, true>) : go(k_observe<Gd, T, true, false>);
+  else En ? go(k_observe<Gd, T, false, true>) : go(k_observe<Gd, T, false, false>);
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 
