@@ -128,8 +128,10 @@ __device__ typename Gd::Link ic_link(const double* __restrict__ phi, int ns, con
   return Gd::mul(UA, UB);
 }
 
+// (launched with 256 threads: the bound lets the compiler use the registers of two waves per
+// SIMD instead of spilling to fit 1024-thread blocks)
 template <typename Gd, typename T>
-__global__ void k_ic_links(const double* __restrict__ phi, int ns, T* __restrict__ U, T* __restrict__ E, Geom g,
+__global__ void __launch_bounds__(256) k_ic_links(const double* __restrict__ phi, int ns, T* __restrict__ U, T* __restrict__ E, Geom g,
                            StepConst c, McvConst mv) {
   constexpr int NG = Gd::NG;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
