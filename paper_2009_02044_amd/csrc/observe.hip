@@ -70,6 +70,69 @@ template <typename G, typename T, bool HAS_EN> struct PassObs {
   }
 };
 
+// Links stored in FP32 are unitary only to the rounding of their stored rows (~1e-7), while
+// 1 - Re Tr U_ij / N_c of a plaquette, which gives B^2, is small: read as stored they bias
+// B^2 (and so eps, p_L, p_T) by ~1e-4 relative.  The pass therefore measures an FP32 state on
+// its links projected onto SU(N) in double precision, every link as it is read; the unitarity
+// observable reads the stored links.
+// The projection of a link onto SU(N): Gram-Schmidt of its two stored rows and the third row
+// rebuilt as for every load.  The reciprocal square roots come from the hardware estimate
+// refined by two Newton steps y <- y (3 - n y^2) / 2 (each doubles the correct bits), without
+// the division and square root of 1 / sqrt(n) and without a branch.
+__device__ __forceinline__ double inv_sqrt_near1(double n) {
+  double y = __builtin_amdgcn_rsq(n);
+  y = y * (1.5 - 0.5 * n * y * y);
+  return y * (1.5 - 0.5 * n * y * y);
+}
+__device__ __forceinline__ void project_near_unitary(M3<double>& r) {
+  double n0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n0 += r.re[0][k] * r.re[0][k] + r.im[0][k] * r.im[0][k];
+  const double s0 = inv_sqrt_near1(n0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { r.re[0][k] *= s0; r.im[0][k] *= s0; }
+  double pr = 0.0, pi = 0.0;   // r0^dag r1
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pr += r.re[0][k] * r.re[1][k] + r.im[0][k] * r.im[1][k];
+    pi += r.re[0][k] * r.im[1][k] - r.im[0][k] * r.re[1][k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.re[1][k] -= pr * r.re[0][k] - pi * r.im[0][k];
+    r.im[1][k] -= pr * r.im[0][k] + pi * r.re[0][k];
+  }
+  double n1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n1 += r.re[1][k] * r.re[1][k] + r.im[1][k] * r.im[1][k];
+  const double s1 = inv_sqrt_near1(n1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { r.re[1][k] *= s1; r.im[1][k] *= s1; }
+  complete_row2(r);
+}
+__device__ __forceinline__ void project_near_unitary(Q2<double>& q) {
+  double n = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) n += q.q[k] * q.q[k];
+  const double s = inv_sqrt_near1(n);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q.q[k] *= s;
+}
+template <typename G, typename T> struct ProjLinks {
+  GlobalLinks<T> f;
+  template <typename L> __device__ __forceinline__ void operator()(L& l, int d, uint32_t s) const {
+    f(l, d, s);
+    if constexpr (sizeof(T) == 4) project_near_unitary(l);
+  }
+};
+template <typename G, typename T, typename Own> struct ProjOwn {
+  const Own& o;
+  __device__ __forceinline__ void operator()(typename G::Link& l, int d) const {
+    o(l, d);
+    if constexpr (sizeof(T) == 4) project_near_unitary(l);
+  }
+};
+
 template <typename G, typename T, bool XS, bool HAS_EN>
 __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, const T* __restrict__ E,
                                                     const T* __restrict__ rhoA, const T* __restrict__ rhoB,
@@ -106,7 +169,9 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
     ob.Vp = Vp;
     ob.c = c;
     ob.trs = trs;
-    plaquette_forces<G, XS, true>(fetch, own, g, x, inv_a2, f, &ob);
+    const ProjLinks<G, T> pfetch{fetch};
+    const ProjOwn<G, T, OwnLinks<G, T, GL_OBS_OWN>> pown{own};
+    plaquette_forces<G, XS, true>(pfetch, pown, g, x, inv_a2, f, &ob);
     double e2[3];
     bool bad = false;
     // one direction at a time (i is a run-time value: members are selected, not indexed)
