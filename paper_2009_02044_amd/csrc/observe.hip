@@ -15,6 +15,7 @@
 // partial sums land in a fixed slot and a single-block pass adds them in a fixed
 // order, so results are bitwise reproducible.
 #include <mutex>
+#include <type_traits>
 #include "internal.h"
 #include "stencil.h"
 #include "reduce.h"
@@ -118,17 +119,60 @@ __device__ __forceinline__ void project_near_unitary(Q2<double>& q) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) q.q[k] *= s;
 }
+// the stored reals of a link (rows 0 and 1, or the quaternion), the layout link_from_stored reads
+__device__ __forceinline__ void link_to_stored(const M3<double>& l, double (&v)[SU3_STORED]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[2 * (3 * r + k)] = l.re[r][k];
+      v[2 * (3 * r + k) + 1] = l.im[r][k];
+    }
+}
+__device__ __forceinline__ void link_to_stored(const Q2<double>& l, double (&v)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = l.q[k];
+}
+
+// The site's own links for an FP32 state: loaded once, projected once, their two rows kept in
+// double precision in a per-thread LDS slot (chunk q of direction d of thread t at
+// [(d NCH + q) OBS_BS + t]) and the link rebuilt from there at every use.
+template <typename G> struct OwnProjLds {
+  static constexpr int W = StoredWidth<typename G::Link>::value;   // 12 or 4 doubles
+  static constexpr int NCH = W / 2;                                // 16-byte chunks
+  double2* lds;
+  uint32_t t;
+  template <typename T>
+  __device__ __forceinline__ OwnProjLds(const GlobalLinks<T>& f, uint32_t s, double2* lds_, uint32_t t_)
+      : lds(lds_), t(t_) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      typename G::Link l;
+      f(l, d, s);
+      project_near_unitary(l);
+      double v[W];
+      link_to_stored(l, v);
+#pragma unroll
+      for (int q = 0; q < NCH; ++q) lds[(d * NCH + q) * OBS_BS + t] = make_double2(v[2 * q], v[2 * q + 1]);
+    }
+  }
+  __device__ __forceinline__ void operator()(typename G::Link& l, int d) const {
+    uint32_t tt = t;
+    asm volatile("" : "+v"(tt));
+    double v[W];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const double2 x = lds[(d * NCH + q) * OBS_BS + tt];
+      v[2 * q] = x.x;
+      v[2 * q + 1] = x.y;
+    }
+    link_from_stored(l, v);
+  }
+};
 template <typename G, typename T> struct ProjLinks {
   GlobalLinks<T> f;
   template <typename L> __device__ __forceinline__ void operator()(L& l, int d, uint32_t s) const {
     f(l, d, s);
-    if constexpr (sizeof(T) == 4) project_near_unitary(l);
-  }
-};
-template <typename G, typename T, typename Own> struct ProjOwn {
-  const Own& o;
-  __device__ __forceinline__ void operator()(typename G::Link& l, int d) const {
-    o(l, d);
     if constexpr (sizeof(T) == 4) project_near_unitary(l);
   }
 };
@@ -145,7 +189,10 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
   const int z = blockIdx.y;
   const int nbx = gridDim.x;
   const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
-  __shared__ typename Vec16<T>::type slot[3 * OwnSlot<G, T>::NCH * OBS_BS];
+  // own-link slots: the stored chunks (FP64 state) or the projected rows in double (FP32 state)
+  constexpr bool PROJ = sizeof(T) == 4;
+  constexpr int SLOT_BYTES = PROJ ? 3 * OwnProjLds<G>::NCH * OBS_BS * 16 : 3 * OwnSlot<G, T>::NCH * OBS_BS * 16;
+  __shared__ double2 slot_mem[SLOT_BYTES / 16];
   __shared__ double trs[3 * OBS_BS];
   const GlobalLinks<T> fetch{U, Vp};
   double acc[NQ];
@@ -160,7 +207,12 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
     x.y = (int)(t / g.nt);
     x.z = z;
     // force terms of the E update, and the forward plaquettes, in double precision
-    const OwnLinks<G, T, GL_OBS_OWN> own(fetch, s, slot, threadIdx.x, OBS_BS);
+    using OwnRaw = OwnLinks<G, T, GL_OBS_OWN>;
+    using Own = std::conditional_t<PROJ, OwnProjLds<G>, OwnRaw>;
+    auto own = [&]() -> Own {
+      if constexpr (PROJ) return Own(fetch, s, slot_mem, threadIdx.x);
+      else return Own(fetch, s, (typename Vec16<T>::type*)slot_mem, threadIdx.x, OBS_BS);
+    }();
     A f[3];
     PassObs<G, T, HAS_EN> ob;
     ob.E = E;
@@ -170,8 +222,7 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
     ob.c = c;
     ob.trs = trs;
     const ProjLinks<G, T> pfetch{fetch};
-    const ProjOwn<G, T, OwnLinks<G, T, GL_OBS_OWN>> pown{own};
-    plaquette_forces<G, XS, true>(pfetch, pown, g, x, inv_a2, f, &ob);
+    plaquette_forces<G, XS, true>(pfetch, own, g, x, inv_a2, f, &ob);
     double e2[3];
     bool bad = false;
     // one direction at a time (i is a run-time value: members are selected, not indexed)
@@ -189,8 +240,8 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
           en.c[k] = eo.c[k] - c.dt / ai * fk;
         }
       }
-      L Ui;
-      own(Ui, i);
+      L Ui;   // the stored link (the unitarity observable reads it as stored)
+      fetch(Ui, i, s);
       if (!HAS_EN && c.hop && i == 2) {
         A rb, ra;
         load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
