@@ -81,7 +81,7 @@ typedef struct {
   void* E;      /* electric field, 3 * n_g * Vp reals */
   void* rhoA;   /* charges of nucleus A, n_g * Vp reals (co-moving storage) */
   void* rhoB;   /* charges of nucleus B, n_g * Vp reals (co-moving storage) */
-  void* work;   /* scratch: initial conditions, reductions, iterations */
+  void* work;   /* scratch: initial conditions, reductions, parked plaquette projections, iterations */
 } glasma_buffers;
 
 /* Initial-condition parameters (Sec. 2 Poisson solution; Sec. 3 eq. single_sheet). */
@@ -217,13 +217,15 @@ int glasma_observe_noalloc(glasma_ctx* ctx, double* d_out);
 
 /* n >= 1 steps, writing to d_out (device, as glasma_observe) the observables of the state
  * the last step starts from: the same as glasma_step(n - 1), glasma_observe,
- * glasma_step(1), up to rounding.  For the FP64 leapfrog with nt a multiple of 64 the last
- * step computes them on the way (a Gauss-residual pass over the state before it, the
- * energy slots inside the step kernel, which has the forces and plaquettes at hand), at a
- * fraction of a separate glasma_observe; the non-finite slot then counts detections (a
- * site may count twice).  For the semi-implicit scheme the observables pass runs between
- * the last step's converged solve and its commit (one solve, not two).  Otherwise it runs
- * exactly that sequence.  Asynchronous for the leapfrog; errors as glasma_step. */
+ * glasma_step(1), up to rounding, without forming the force twice.  Leapfrog: a pass over
+ * the state before the last step sums what that state fixes (Gauss residual, B^2, the
+ * E(t - dt/2) halves of E^2 and S_L, unitarity) and parks two plaquette projections in the
+ * work buffer; after the step a second pass adds the E(t + dt/2) halves, E(t + dt/2) being
+ * the step's own (for FP32 storage its FP32 update).  For FP64 with nt a multiple of 64 the
+ * step kernel itself adds the energy slots after a Gauss-residual pass.  The non-finite
+ * slot counts detections (a site may count twice).  For the semi-implicit scheme the
+ * observables pass runs between the last step's converged solve and its commit (one solve,
+ * not two).  Asynchronous for the leapfrog; errors as glasma_step. */
 int glasma_step_observe(glasma_ctx* ctx, int32_t n, double* d_out);
 
 /* Local rest frame of every layer (Sec. 4: the local energy density from diagonalising

@@ -133,8 +133,11 @@ static SemiRegion semi_region(const glasma_params* p) {
   s.end = s.conv + SEMI_SLOTS * 2 * sizeof(double);
   return s;
 }
+// Leapfrog: after the general region, the projections parked by the observing step's first
+// pass (obs_split_scratch_elems reals of the state's precision).
 static size_t work_bytes(const glasma_params* p) {
-  return p->scheme == 1 ? semi_region(p).end : general_bytes(p);
+  if (p->scheme == 1) return semi_region(p).end;
+  return general_bytes(p) + align256(obs_split_scratch_elems(geom_of(p), p->nc * p->nc - 1) * elem(p));
 }
 
 template <class F> static int dispatch(glasma_ctx* c, F&& f) {
@@ -470,11 +473,18 @@ int glasma_step(glasma_ctx* c, int32_t n) {
   return advance(c, n);
 }
 
-// One step; with d_obs (the observing step: FP64 leapfrog with nt a multiple of 64, or the
-// semi-implicit scheme) it also writes to d_obs the observables of the state it starts from:
-// for the leapfrog the Gauss residual kernel runs first on that state and the step kernel
-// adds the energy slots; for the semi-implicit scheme the observables pass runs between the
-// converged solve and its commit, with E(t + dt/2) from the solve.
+// Which observing step the FP64 leapfrog takes where the step kernel can gather the energy
+// slots itself (nt a multiple of 64): 1 that fused step, 0 the passes around a plain step.
+#ifndef GL_OBS_FUSED64
+#define GL_OBS_FUSED64 1
+#endif
+
+// One step; with d_obs (the observing step) it also writes to d_obs the observables of the
+// state it starts from.  Leapfrog: a pass over that state (Gauss residual, magnetic and
+// E(t - dt/2) parts, parked plaquette projections), the plain step, and a pass adding the
+// E(t + dt/2) parts; or, for FP64 with nt a multiple of 64, the Gauss residual kernel and a
+// step kernel that adds the energy slots.  Semi-implicit scheme: the observables pass runs
+// between the converged solve and its commit, with E(t + dt/2) from the solve.
 static int one_step(glasma_ctx* c, double* d_obs) {
   StepConst sc = step_const(c);
   // reunitarisation after this step: inside the plain leapfrog step, else a pass after it
@@ -486,6 +496,17 @@ static int one_step(glasma_ctx* c, double* d_obs) {
     if (rc) return rc;
     if (d_obs && (rc = semi_observe_solved(c, sc, d_obs))) return rc;
     if ((rc = semi_commit(c, sc, links))) return rc;
+  } else if (d_obs && !(GL_OBS_FUSED64 && c->p.fp == 64 && fused_observe_geometry(c->g))) {
+    double* partial = (double*)c->b.work;
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      T* Q = (T*)((char*)c->b.work + general_bytes(&c->p));
+      launch_obs_pre<G, T>(cur_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, Q, partial, c->stream);
+      launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc, ru,
+                            c->stream);
+      launch_obs_post<G, T>((T*)c->b.E, Q, c->g, sc, partial, d_obs, c->stream);
+      return 0;
+    });
+    ru_done = ru;
   } else if (d_obs) {
     double* partial = (double*)c->b.work;
     dispatch(c, [&]<typename G, typename T>() -> int {
@@ -537,10 +558,7 @@ int glasma_step_observe(glasma_ctx* c, int32_t n, double* d_out) {
   c->adj_ok = false;
   int rc = advance(c, n - 1);
   if (rc) return rc;
-  if (c->p.scheme == 1 || (c->p.fp == 64 && fused_observe_geometry(c->g))) return one_step(c, d_out);
-  rc = glasma_observe(c, d_out);
-  if (rc) return rc;
-  return advance(c, 1);
+  return one_step(c, d_out);
 }
 
 int glasma_reunitarize(glasma_ctx* c) {

@@ -63,6 +63,17 @@ void launch_leapfrog_observe(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const 
                              double* partial, hipStream_t st);
 void launch_observe_finish(const double* partial, int nbx, const Geom& g, const StepConst& c, double* out,
                            hipStream_t st);
+// Observing step around a plain leapfrog step (any geometry and precision): launch_obs_pre on
+// the state before the step (partial sums as launch_observe; Q: obs_split_scratch_elems
+// reals of the state's precision), the step, then launch_obs_post (partial sums completed
+// and finished into out).
+size_t obs_split_scratch_elems(const Geom& g, int ng);
+template <typename G, typename T>
+void launch_obs_pre(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c, T* Q,
+                    double* partial, hipStream_t st);
+template <typename G, typename T>
+void launch_obs_post(const T* E, const T* Q, const Geom& g, const StepConst& c, double* partial, double* out,
+                     hipStream_t st);
 // event averages of a batch's observables (class averages per N_z, common z / N_z grid)
 struct BatchObsEvent {
   int64_t off;   // doubles from the start of the observables region

@@ -452,6 +452,215 @@ void launch_observe_finish(const double* partial, int nbx, const Geom& g, const 
   hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
 }
 
+// ---- the observing step around a plain step (leapfrog; any geometry and precision) ----
+// The observables of the state (U(t), E(t - dt/2), rho(t - dt/2)) that a step starts from,
+// split around that step so that neither the step nor a separate pass forms the force twice:
+//  - k_obs_pre, before the step, sums what that state fixes: the Gauss residual, |rho|^2,
+//    B^2 from the forward plaquettes, the E(t - dt/2) halves of E^2 and of S_L, link
+//    unitarity and the non-finite count.  It parks the two projections that S_L pairs with
+//    E(t + dt/2), q_x = P(U_{x,z}) / (2 a_x a_z) and q_y = P(U_{y,z}) / (2 a_y a_z), in a
+//    work buffer laid out as the x and y directions of an E field;
+//  - the plain step writes E(t + dt/2), its hop current included;
+//  - k_obs_post adds the E(t + dt/2) halves of E^2 and S_L to the same per-block sums.
+// E^2 = (|E(t - dt/2)|^2 + |E(t + dt/2)|^2)/2 and S_L = sum_{i = x, y} Ebar_i . P(U_{i,z}) /
+// (a_i a_z) are linear in the two half steps, so the sums split exactly (up to rounding).
+// The plaquettes of an FP32 state are formed on links projected onto SU(N) in double
+// precision, as in the standalone pass; unitarity and the Gauss residual read the links as
+// stored.  Both passes cover a layer with obs_blocks_per_layer blocks, the same slots.
+template <typename G, typename T, bool XS>
+__global__ void __launch_bounds__(OBS_BS, 2) k_obs_pre(const T* __restrict__ U, const T* __restrict__ E,
+                                                    const T* __restrict__ rhoA, const T* __restrict__ rhoB,
+                                                    Geom g, StepConst c, T* __restrict__ Q,
+                                                    double* __restrict__ partial) {
+  using L = typename G::Link;   // double precision group
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t Vp = g.Vp;
+  const int z = blockIdx.y;
+  const int nbx = gridDim.x;
+  constexpr bool PROJ = sizeof(T) == 4;
+  constexpr int SLOT_BYTES = PROJ ? 3 * OwnProjLds<G>::NCH * OBS_BS * 16 : 3 * OwnSlot<G, T>::NCH * OBS_BS * 16;
+  __shared__ double2 slot_mem[SLOT_BYTES / 16];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  // blocks start at multiples of 64 sites of the layer, so rows stay whole for XS
+  const int64_t t = (int64_t)blockIdx.x * OBS_BS + threadIdx.x;
+  if (t < g.layer) {
+    const uint32_t s = (uint32_t)((int64_t)z * g.layer + t);
+    Site x;
+    x.x = (int)(t % g.nt);
+    x.y = (int)(t / g.nt);
+    x.z = z;
+    const GlobalLinks<T> fetch{U, Vp};
+    const ProjLinks<G, T> pfetch{fetch};
+    // own links parked in LDS (projected onto SU(N) in double for FP32 storage), neighbour
+    // links projected as they are read; a scheduling fence between the planes keeps the
+    // compiler from hoisting every load to the top
+    using OwnRaw = OwnLinks<G, T, OWN_LDS>;
+    using Own = std::conditional_t<PROJ, OwnProjLds<G>, OwnRaw>;
+    auto own = [&]() -> Own {
+      if constexpr (PROJ) return Own(fetch, s, slot_mem, threadIdx.x);
+      else return Own(fetch, s, (typename Vec16<T>::type*)slot_mem, threadIdx.x, OBS_BS);
+    }();
+    bool bad = false;
+    XNbr xn;
+    if constexpr (XS) xn = x_nbr(g, x);
+    const uint32_t sx = idx(g, shifted(g, x, 0, +1));
+    const uint32_t sy = idx(g, shifted(g, x, 1, +1));
+    const uint32_t sz = idx(g, shifted(g, x, 2, +1));
+    const double nc = (double)G::NC;
+    const double inv_a2[3] = {1.0 / (c.a[0] * c.a[0]), 1.0 / (c.a[1] * c.a[1]), 1.0 / (c.a[2] * c.a[2])};
+    double BL2, BT2 = 0.0, sl = 0.0, n2[3];
+    {
+      // (x, y): U_{x,y} = U_x(x) U_y(x+x) U_x(x+y)^dag U_y(x)^dag, its trace only
+      L Oi, Oj, Nx, Nb;
+      own(Oi, 0);
+      own(Oj, 1);
+      if constexpr (XS) Nx = pull_link(Oj, xn.ap);
+      else pfetch(Nx, 1, sx);
+      pfetch(Nb, 0, sy);
+      double tr = 0.0;
+      (void)G::proj_retr_mul_dag(G::mul_dag(G::mul(Oi, Nx), Nb), Oj, tr);
+      BL2 = 4.0 * inv_a2[0] * inv_a2[1] * (nc - tr);
+    }
+    staple_fence<true>();
+    // (x, z) and (y, z): traces for B_T^2, projections for S_L
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      L Oi, Oz, Nx, Nb;
+      own(Oi, i);
+      own(Oz, 2);
+      if (i == 0) {
+        if constexpr (XS) Nx = pull_link(Oz, xn.ap);
+        else pfetch(Nx, 2, sx);
+      } else {
+        pfetch(Nx, 2, sy);
+      }
+      pfetch(Nb, i, sz);
+      double tr = 0.0;
+      const A p = G::proj_retr_mul_dag(G::mul_dag(G::mul(Oi, Nx), Nb), Oz, tr);
+      BT2 += 4.0 * inv_a2[i] * inv_a2[2] * (nc - tr);
+      const double h = 0.5 / (c.a[i] * c.a[2]);
+      A q, eo;
+      load_alg(eo, E, i, s, Vp);
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        q.c[k] = h * p.c[k];
+        sl += eo.c[k] * q.c[k];
+        bad |= !isfinite(eo.c[k]);
+      }
+      n2[i] = norm2(eo);
+      store_alg(q, Q, i, s, Vp);
+      staple_fence<true>();
+    }
+    {
+      A eo;
+      load_alg(eo, E, 2, s, Vp);
+#pragma unroll
+      for (int k = 0; k < NG; ++k) bad |= !isfinite(eo.c[k]);
+      n2[2] = norm2(eo);
+    }
+    const double EL2 = 0.5 * n2[2], ET2 = 0.5 * (n2[0] + n2[1]);
+    acc[Q_EPS] = 0.5 * (EL2 + ET2 + BL2 + BT2);
+    acc[Q_PL] = 0.5 * (ET2 + BT2 - EL2 - BL2);
+    acc[Q_PT] = 0.5 * (EL2 + BL2);
+    acc[Q_SL] = sl;
+    // Gauss residual at (U(t), E(t - dt/2), rho(t - dt/2)); unitarity of the stored links
+    A G_, r, rb;
+    load_alg(r, rhoA, 0, site_index(g, x.x, x.y, slotA(z, c.offA, g.nz)), Vp);
+    load_alg(rb, rhoB, 0, site_index(g, x.x, x.y, slotB(z, c.offB, g.nz)), Vp);
+    for (int k = 0; k < NG; ++k) { r.c[k] += rb.c[k]; G_.c[k] = -r.c[k]; }
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      const double ai = i == 0 ? c.a[0] : (i == 1 ? c.a[1] : c.a[2]);
+      const uint32_t sm = idx(g, shifted(g, x, i, -1));
+      L Um;
+      load_link(Um, U, i, sm, Vp);
+      A eh, em;
+      load_alg(eh, E, i, s, Vp);
+      load_alg(em, E, i, sm, Vp);
+      const A tt = G::transport(Um, em);
+      for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tt.c[k]) / ai;
+      L Ui;
+      fetch(Ui, i, s);
+      const double uv = G::unit_violation(Ui);
+      bad |= !isfinite(uv);
+      acc[Q_UNIT] = fmax(acc[Q_UNIT], uv);
+    }
+    acc[Q_G2] = norm2(G_);
+    acc[Q_RHO2] = norm2(r);
+    double gm = 0.0;
+    for (int k = 0; k < NG; ++k) gm = fmax(gm, fabs(G_.c[k]));
+    acc[Q_GMAX] = gm;
+    bad |= !isfinite(acc[Q_EPS]) || !isfinite(acc[Q_G2]);
+    acc[Q_BAD] = bad ? 1.0 : 0.0;
+  }
+  block_reduce_write<OBS_BS>(acc, Q_ALL, partial + ((int64_t)z * nbx + blockIdx.x) * NQ);
+}
+
+template <typename G, typename T>
+__global__ void __launch_bounds__(OBS_BS) k_obs_post(const T* __restrict__ E, const T* __restrict__ Q, Geom g,
+                                                     double* __restrict__ partial) {
+  using A = typename G::Alg;
+  constexpr int NG = G::NG;
+  const int64_t Vp = g.Vp;
+  const int z = blockIdx.y;
+  const int nbx = gridDim.x;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  const int64_t t = (int64_t)blockIdx.x * OBS_BS + threadIdx.x;
+  if (t < g.layer) {
+    const uint32_t s = (uint32_t)((int64_t)z * g.layer + t);
+    double n2[3], sl = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      A en;
+      load_alg_own(en, E, i, s, Vp);
+#pragma unroll
+      for (int k = 0; k < NG; ++k) bad |= !isfinite(en.c[k]);
+      n2[i] = norm2(en);
+      if (i < 2) {
+        A q;
+        load_alg_own(q, Q, i, s, Vp);
+#pragma unroll
+        for (int k = 0; k < NG; ++k) sl += en.c[k] * q.c[k];
+      }
+    }
+    const double EL2 = 0.5 * n2[2], ET2 = 0.5 * (n2[0] + n2[1]);
+    acc[Q_EPS] = 0.5 * (EL2 + ET2);
+    acc[Q_PL] = 0.5 * (ET2 - EL2);
+    acc[Q_PT] = 0.5 * EL2;
+    acc[Q_SL] = sl;
+    acc[Q_BAD] = (bad || !isfinite(sl)) ? 1.0 : 0.0;
+  }
+  constexpr unsigned M = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_BAD);
+  block_reduce_write<OBS_BS, M>(acc, M, partial + ((int64_t)z * nbx + blockIdx.x) * NQ);
+}
+
+size_t obs_split_scratch_elems(const Geom& g, int ng) { return (size_t)2 * ng * g.Vp; }
+
+template <typename G, typename T>
+void launch_obs_pre(const T* U, const T* E, const T* rhoA, const T* rhoB, const Geom& g, const StepConst& c, T* Q,
+                    double* partial, hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const dim3 grid(obs_blocks_per_layer(g), g.nz);
+  if (rows_in_wavefronts(g.nt))
+    hipLaunchKernelGGL((k_obs_pre<Gd, T, true>), grid, dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, Q, partial);
+  else
+    hipLaunchKernelGGL((k_obs_pre<Gd, T, false>), grid, dim3(OBS_BS), 0, st, U, E, rhoA, rhoB, g, c, Q, partial);
+}
+template <typename G, typename T>
+void launch_obs_post(const T* E, const T* Q, const Geom& g, const StepConst& c, double* partial, double* out,
+                     hipStream_t st) {
+  using Gd = typename GroupOf<G::NC, double>::type;
+  const int nbx = obs_blocks_per_layer(g);
+  hipLaunchKernelGGL((k_obs_post<Gd, T>), dim3(nbx, g.nz), dim3(OBS_BS), 0, st, E, Q, g, partial);
+  hipLaunchKernelGGL(k_observe_finish, dim3(1), dim3(256), 0, st, partial, nbx, g, c, out);
+}
+
 // ---- local rest frame per layer (Sec. 4) ----------------------------------------
 // eps_loc and the frame velocity v along +z from the timelike eigenvector of the (t, z)
 // block of T^mu_nu, [[eps, -S_L], [S_L, -p_L]]:  S_L v^2 - (eps + p_L) v + S_L = 0.
@@ -577,7 +786,11 @@ void launch_reunit(T* U, const Geom& g, hipStream_t st) {
                                      hipStream_t);                                                          \
   template void launch_reunit<G, T>(T*, const Geom&, hipStream_t);                                        \
   template void launch_obs_gauss<G, T>(const T*, const T*, const T*, const T*, const Geom&, const StepConst&, \
-                                       double*, hipStream_t);
+                                       double*, hipStream_t);                                             \
+  template void launch_obs_pre<G, T>(const T*, const T*, const T*, const T*, const Geom&, const StepConst&, T*, \
+                                     double*, hipStream_t);                                               \
+  template void launch_obs_post<G, T>(const T*, const T*, const Geom&, const StepConst&, double*, double*,   \
+                                      hipStream_t);
 GL_INST(Su2<double>, double)
 GL_INST(Su3<double>, double)
 GL_INST(Su2<float>, float)

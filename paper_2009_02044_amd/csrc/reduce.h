@@ -22,10 +22,10 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Reduce the slots of acc selected by the bit mask over a work-group of BS threads
 // (64-lane shuffles, then the wavefronts in a fixed order through LDS) and write them to
-// dst[q]; with ADD_BAD the slot Q_BAD is added to what dst already holds.  Every thread
-// of the work-group must call it.
+// dst[q]; the slots selected by the bit mask ADD are added to what dst already holds.  Every
+// thread of the work-group must call it.
 constexpr unsigned Q_ALL = (1u << NQ) - 1;
-template <int BS, bool ADD_BAD = false>
+template <int BS, unsigned ADD = 0u>
 __device__ __forceinline__ void block_reduce_write(const double (&acc)[NQ], unsigned mask, double* dst) {
   __shared__ double red[BS / 64][NQ];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -40,7 +40,7 @@ __device__ __forceinline__ void block_reduce_write(const double (&acc)[NQ], unsi
     const int q = threadIdx.x;
     double v = red[0][q];
     for (int w = 1; w < BS / 64; ++w) v = q_is_max(q) ? fmax(v, red[w][q]) : v + red[w][q];
-    if (ADD_BAD && q == Q_BAD) v += dst[q];
+    if ((ADD >> q) & 1u) v += dst[q];
     dst[q] = v;
   }
 }

@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const
     uint32_t slot;
     col_map_block(m, blockIdx.x, zb, slot);
     const unsigned mask = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_UNIT) | (1u << Q_BAD);
-    block_reduce_write<LF_BS, true>(acc, mask, partial + ((int64_t)x.z * col_map_slots_per_layer(m) + slot) * NQ);
+    block_reduce_write<LF_BS, 1u << Q_BAD>(acc, mask, partial + ((int64_t)x.z * col_map_slots_per_layer(m) + slot) * NQ);
   }
 }
 

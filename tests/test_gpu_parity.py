@@ -422,13 +422,17 @@ def test_rest_frame_against_oracle():
 
 @pytest.mark.parametrize("n", [5, 6])
 @pytest.mark.parametrize("nc,nz,nt,fp", [(3, 4, 64, 64), (2, 4, 64, 64), (3, 2, 128, 64), (3, 6, 8, 64),
-                                         (3, 4, 64, 32)])
+                                         (3, 5, 12, 64), (2, 4, 12, 64), (3, 4, 64, 32), (3, 3, 12, 32),
+                                         (2, 4, 8, 32)])
 def test_step_observe_equals_step_then_observe(nc, nz, nt, fp, n):
     """glasma_step_observe(n) against glasma_step(n - 1), glasma_observe, glasma_step(1):
-    the same observables (the FP64 cases with nt a multiple of 64 take the observing step:
-    Gauss pass plus energy slots inside the step kernel, x neighbours from adjacent lanes at
-    nt = 64 and from memory at nt = 128) and the same final state; the observing step is a
-    step without a hop for n = 5 and one with a hop for n = 6 (hops on odd step indices)."""
+    the same observables and the same final state.  The FP64 cases with nt a multiple of 64
+    take the fused observing step (Gauss pass plus energy slots inside the step kernel, x
+    neighbours from adjacent lanes at nt = 64 and from memory at nt = 128); the others the
+    passes around a plain step (x neighbours from adjacent lanes at nt = 8 and 64, from memory
+    at nt = 12), whose E(t + dt/2) is the step's own (in FP32 its FP32 update, where the
+    standalone pass recomputes it in double).  The observing step is a step without a hop for
+    n = 5 and one with a hop for n = 6 (hops on odd step indices)."""
     pkg = lattice_or_skip()
     import torch
     say(f"case: step_observe su{nc} {nz}x{nt}x{nt} fp{fp} n={n}")
