@@ -306,7 +306,7 @@ def run_batched(steps, warmup, graph_chunk=16, n_grid=64, compare_fp64=True):
 
     b, init = make(32)
     init()
-    tune = b.autotune(steps=2)
+    tune = b.autotune(steps=4)
     init()
     b.run(warmup, graph_chunk=0)
     b.stream.synchronize()

@@ -377,12 +377,14 @@ int glasma_batch_classes(const glasma_batch* b, int32_t* n_classes, int32_t* nz_
 int glasma_batch_observe(glasma_batch* b, int32_t n_grid, double* class_avg, double* grid_avg, double* per_event);
 
 /* Work-item tiling: sites per item (64, 128 or 256 threads per workgroup) and the
- * number of persistent workgroups (0: one workgroup per item). */
+ * number of persistent workgroups that loop over the items, or 0: one workgroup per item,
+ * a kernel without the loop (for FP32 it fits four waves per SIMD, the looping one three). */
 int glasma_batch_set_tiling(glasma_batch* b, int32_t sites_per_item, int32_t grid);
 
-/* Autotuner: times every tiling candidate over `steps` steps (HIP events) and keeps the
- * fastest; writes a JSON report (may be NULL).  Advances the state by 13 * steps steps,
- * so call it before setting up the events that are to be measured. */
+/* Autotuner: times every tiling candidate (12: sites per item 64, 128, 256 x grid 0, 4096,
+ * 2048, 1024) over `steps` steps (HIP events, after one untimed step of that candidate)
+ * and keeps the fastest; writes a JSON report (may be NULL).  Advances the state by
+ * 13 * steps + 12 steps, so call it before setting up the events that are to be measured. */
 int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t report_len);
 
 /* Host-side evaluation of the library's group kernels, for CPU tests of the

@@ -1044,11 +1044,11 @@ static int batch_prepare(glasma_batch* b, int bs, BatchConst* bc) {
   return GLASMA_OK;
 }
 
+// grid 0: one work-group per item (no loop); grid > 0: that many persistent work-groups
 static void batch_launch_one(glasma_batch* b, const BatchConst& bc, int bs, int grid) {
-  const int g = grid > 0 ? grid : (int)bc.items;
   glasma_ctx* c0 = b->ev[0];
   dispatch(c0, [&]<typename G, typename T>() -> int {
-    launch_batch_step<G, T>(b->pool, b->d_ev, b->d_item_event, bc, b->d_ctr, g, bs, b->stream);
+    launch_batch_step<G, T>(b->pool, b->d_ev, b->d_item_event, bc, b->d_ctr, grid, bs, b->stream);
     return 0;
   });
   launch_batch_tick(b->d_ctr, b->stream);
@@ -1108,8 +1108,9 @@ int glasma_batch_set_tiling(glasma_batch* b, int32_t sites_per_item, int32_t gri
   return GLASMA_OK;
 }
 
-// Time every (sites per item, grid) candidate over `steps` steps with HIP events and
-// keep the fastest; the state advances by (candidates + 1) * steps steps.
+// Time every (sites per item, grid) candidate over `steps` steps with HIP events, after one
+// untimed step of that candidate (its first launch pays for loading the kernel), and keep
+// the fastest; the state advances by steps + candidates * (steps + 1) steps.
 int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t report_len) {
   if (!b) return fail(nullptr, GLASMA_E_ARG, "NULL batch");
   if (steps < 1) return bfail(b, GLASMA_E_ARG, "steps must be >= 1");
@@ -1129,6 +1130,8 @@ int glasma_batch_autotune(glasma_batch* b, int32_t steps, char* report, size_t r
     for (int gr : grids) {
       b->bs = bs;
       b->grid = gr;
+      rc = glasma_batch_run(b, 1, 0);
+      if (rc) return rc;
       BHIPCHK(b, hipEventRecord(e0, b->stream));
       rc = glasma_batch_run(b, steps, 0);
       if (rc) return rc;

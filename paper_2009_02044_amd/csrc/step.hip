@@ -278,46 +278,79 @@ template void launch_leapfrog_observe<Su2<double>, double>(const double*, double
 // parity of the link buffers, hop flag and charge offsets all follow from it.
 GL_HD int64_t hop_count_dev(int64_t s, int64_t p, int64_t q) { return ((2 * s + 1) * p + q) / (2 * q); }
 
+// Per-step values of the batch, from the device step counter.
+struct BatchStep {
+  int64_t st, S0;
+  bool hop, reunit;
+  double inv_a2[3];
+};
+__device__ __forceinline__ BatchStep batch_step_of(const BatchConst& bc, const int64_t* __restrict__ ctr) {
+  BatchStep b;
+  b.st = ctr[0];
+  const int64_t S1 = hop_count_dev(b.st, bc.hop_p, bc.hop_q);
+  b.S0 = hop_count_dev(b.st - 1, bc.hop_p, bc.hop_q);
+  b.hop = S1 > b.S0;
+  b.reunit = bc.reunit_every > 0 && ((b.st + 1) % bc.reunit_every) == 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) b.inv_a2[k] = 1.0 / (bc.a[k] * bc.a[k]);
+  return b;
+}
+
+// One work item: blockDim.x consecutive sites of one event.
+template <typename G, typename T>
+__device__ __forceinline__ void batch_item(char* __restrict__ pool, const EventDesc* __restrict__ ev,
+                                           const uint32_t* __restrict__ item_event, const BatchConst& bc,
+                                           const BatchStep& b, uint32_t item, typename Vec16<T>::type* slot) {
+  const EventDesc d = ev[item_event[item]];
+  const uint32_t s = (item - d.item0) * blockDim.x + threadIdx.x;
+  if (s >= (uint32_t)d.g.V) return;
+  StepConst c;
+  c.a[0] = bc.a[0]; c.a[1] = bc.a[1]; c.a[2] = bc.a[2];
+  c.dt = bc.dt;
+  c.hop = b.hop ? 1 : 0;
+  const int64_t off = (d.off0 + (b.S0 - d.hops0)) % d.g.nz;
+  c.offA = (int)off;
+  c.offB = (int)off;
+  c.scheme = 0;
+  const bool odd = (b.st & 1) != 0;
+  const T* U = (const T*)(pool + (odd ? d.Uodd : d.Ueven));
+  T* Un = (T*)(pool + (odd ? d.Ueven : d.Uodd));
+  Site x;
+  x.x = (int)(s % (uint32_t)d.g.nt);
+  x.y = (int)((s / (uint32_t)d.g.nt) % (uint32_t)d.g.nt);
+  x.z = (int)(s / (uint32_t)d.g.layer);
+  // item = 64-aligned sites of one event: rows lie in wavefronts when nt divides 64
+  constexpr int K = OwnMode<G, T>::value;
+  T *E = (T*)(pool + d.E), *rA = (T*)(pool + d.rhoA), *rB = (T*)(pool + d.rhoB);
+  const uint32_t TB = blockDim.x;
+  const Geom g = d.g;
+  // the hop branch inside is uniform over the launch (HOP = true only enables it)
+  if (rows_in_wavefronts(g.nt))
+    update_site<G, T, true, true, K>(U, Un, E, rA, rB, g, c, b.inv_a2, x, s, b.reunit, slot, TB);
+  else
+    update_site<G, T, true, false, K>(U, Un, E, rA, rB, g, c, b.inv_a2, x, s, b.reunit, slot, TB);
+}
+
+// Persistent form: `grid` work-groups loop over the items.
 template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_batch_step(char* __restrict__ pool, const EventDesc* __restrict__ ev,
                                                     const uint32_t* __restrict__ item_event, BatchConst bc,
                                                     const int64_t* __restrict__ ctr) {
-  const int64_t st = ctr[0];
-  const int64_t S1 = hop_count_dev(st, bc.hop_p, bc.hop_q), S0 = hop_count_dev(st - 1, bc.hop_p, bc.hop_q);
-  const bool hop = S1 > S0;
-  const bool reunit = bc.reunit_every > 0 && ((st + 1) % bc.reunit_every) == 0;
-  const double inv_a2[3] = {1.0 / (bc.a[0] * bc.a[0]), 1.0 / (bc.a[1] * bc.a[1]), 1.0 / (bc.a[2] * bc.a[2])};
+  const BatchStep b = batch_step_of(bc, ctr);
   __shared__ typename Vec16<T>::type slot[OwnLds<G, T, 256>::N];
-  for (uint32_t item = blockIdx.x; item < bc.items; item += gridDim.x) {
-    const EventDesc d = ev[item_event[item]];
-    const uint32_t s = (item - d.item0) * blockDim.x + threadIdx.x;
-    if (s >= (uint32_t)d.g.V) continue;
-    StepConst c;
-    c.a[0] = bc.a[0]; c.a[1] = bc.a[1]; c.a[2] = bc.a[2];
-    c.dt = bc.dt;
-    c.hop = hop ? 1 : 0;
-    const int64_t off = (d.off0 + (S0 - d.hops0)) % d.g.nz;
-    c.offA = (int)off;
-    c.offB = (int)off;
-    c.scheme = 0;
-    const bool odd = (st & 1) != 0;
-    const T* U = (const T*)(pool + (odd ? d.Uodd : d.Ueven));
-    T* Un = (T*)(pool + (odd ? d.Ueven : d.Uodd));
-    Site x;
-    x.x = (int)(s % (uint32_t)d.g.nt);
-    x.y = (int)((s / (uint32_t)d.g.nt) % (uint32_t)d.g.nt);
-    x.z = (int)(s / (uint32_t)d.g.layer);
-    // item = 64-aligned sites of one event: rows lie in wavefronts when nt divides 64
-    constexpr int K = OwnMode<G, T>::value;
-    T *E = (T*)(pool + d.E), *rA = (T*)(pool + d.rhoA), *rB = (T*)(pool + d.rhoB);
-    const uint32_t TB = blockDim.x;
-    const Geom g = d.g;
-    // the hop branch inside is uniform over the launch (HOP = true only enables it)
-    if (rows_in_wavefronts(g.nt))
-      update_site<G, T, true, true, K>(U, Un, E, rA, rB, g, c, inv_a2, x, s, reunit, slot, TB);
-    else
-      update_site<G, T, true, false, K>(U, Un, E, rA, rB, g, c, inv_a2, x, s, reunit, slot, TB);
-  }
+  for (uint32_t item = blockIdx.x; item < bc.items; item += gridDim.x)
+    batch_item<G, T>(pool, ev, item_event, bc, b, item, slot);
+}
+
+// One work-group per item.  Without the loop the FP32 kernel fits 128 registers and runs at
+// four waves per SIMD (the loop costs it ~23 registers and a wave).
+template <typename G, typename T>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1)
+    k_batch_step_flat(char* __restrict__ pool, const EventDesc* __restrict__ ev,
+                      const uint32_t* __restrict__ item_event, BatchConst bc, const int64_t* __restrict__ ctr) {
+  const BatchStep b = batch_step_of(bc, ctr);
+  __shared__ typename Vec16<T>::type slot[OwnLds<G, T, 256>::N];
+  if (blockIdx.x < bc.items) batch_item<G, T>(pool, ev, item_event, bc, b, blockIdx.x, slot);
 }
 
 // advance the device step counter (one lane writes)
@@ -331,8 +364,12 @@ __global__ void k_batch_tick(int64_t* ctr) {
 template <typename G, typename T>
 void launch_batch_step(char* pool, const EventDesc* ev, const uint32_t* item_event, const BatchConst& bc,
                        const int64_t* ctr, int grid, int bs, hipStream_t st) {
-  hipLaunchKernelGGL((k_batch_step<G, T>), dim3((unsigned)grid), dim3((unsigned)bs), 0, st, pool, ev, item_event, bc,
-                     ctr);
+  if (grid > 0)
+    hipLaunchKernelGGL((k_batch_step<G, T>), dim3((unsigned)grid), dim3((unsigned)bs), 0, st, pool, ev, item_event, bc,
+                       ctr);
+  else
+    hipLaunchKernelGGL((k_batch_step_flat<G, T>), dim3(bc.items), dim3((unsigned)bs), 0, st, pool, ev, item_event,
+                       bc, ctr);
 }
 void launch_batch_tick(int64_t* ctr, hipStream_t st) { hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, st, ctr); }
 
