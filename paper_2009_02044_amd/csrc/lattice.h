@@ -256,6 +256,17 @@ GL_HD uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   const uint32_t q = nb / NXCD, r = nb % NXCD, x = b % NXCD;
   return x * q + (x < r ? x : r) + b / NXCD;
 }
+// The same in chunks of C consecutive indices dealt to the XCDs in turn: work-group b (XCD
+// b mod 8) takes index ((j / C) 8 + b mod 8) C + j mod C, j = b / 8, over the largest
+// multiple of 8 C below nb (the rest keeps its own index).  A chunk keeps its y and z
+// neighbours in one L2 while every XCD still gets a share of every part of [0, nb) (the
+// batched step: events of unequal cost per item).  A bijection of [0, nb).
+template <uint32_t C> GL_HD uint32_t xcd_chunk_remap(uint32_t b, uint32_t nb) {
+  const uint32_t whole = nb / (NXCD * C) * (NXCD * C);
+  if (b >= whole) return b;
+  const uint32_t x = b % NXCD, j = b / NXCD;
+  return ((j / C) * NXCD + x) * C + j % C;
+}
 
 // Placement of the step's work-groups on the XCDs (work-group b runs on XCD b mod 8,
 // each XCD has its own L2).  Two decompositions:

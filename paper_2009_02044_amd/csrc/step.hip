@@ -331,15 +331,20 @@ __device__ __forceinline__ void batch_item(char* __restrict__ pool, const EventD
     update_site<G, T, true, false, K>(U, Un, E, rA, rB, g, c, b.inv_a2, x, s, b.reunit, slot, TB);
 }
 
-// Persistent form: `grid` work-groups loop over the items.
+// Items are dealt to the XCDs in chunks of 64 (xcd_chunk_remap): 2.5% faster than one by one
+// on a mix of 64 events, which keeps the XCDs' shares of the events balanced.
+constexpr uint32_t BATCH_XCD_CHUNK = 64;
+
+// Persistent form: `grid` work-groups loop over the items (a grid that is a multiple of 8
+// keeps each work-group's indices on its own XCD).
 template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_batch_step(char* __restrict__ pool, const EventDesc* __restrict__ ev,
                                                     const uint32_t* __restrict__ item_event, BatchConst bc,
                                                     const int64_t* __restrict__ ctr) {
   const BatchStep b = batch_step_of(bc, ctr);
   __shared__ typename Vec16<T>::type slot[OwnLds<G, T, 256>::N];
-  for (uint32_t item = blockIdx.x; item < bc.items; item += gridDim.x)
-    batch_item<G, T>(pool, ev, item_event, bc, b, item, slot);
+  for (uint32_t v = blockIdx.x; v < bc.items; v += gridDim.x)
+    batch_item<G, T>(pool, ev, item_event, bc, b, xcd_chunk_remap<BATCH_XCD_CHUNK>(v, bc.items), slot);
 }
 
 // One work-group per item.  Without the loop the FP32 kernel fits 128 registers and runs at
@@ -350,7 +355,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1)
                       const uint32_t* __restrict__ item_event, BatchConst bc, const int64_t* __restrict__ ctr) {
   const BatchStep b = batch_step_of(bc, ctr);
   __shared__ typename Vec16<T>::type slot[OwnLds<G, T, 256>::N];
-  if (blockIdx.x < bc.items) batch_item<G, T>(pool, ev, item_event, bc, b, blockIdx.x, slot);
+  if (blockIdx.x < bc.items)
+    batch_item<G, T>(pool, ev, item_event, bc, b, xcd_chunk_remap<BATCH_XCD_CHUNK>(blockIdx.x, bc.items), slot);
 }
 
 // advance the device step counter (one lane writes)
