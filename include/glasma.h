@@ -222,7 +222,8 @@ int glasma_observe_noalloc(glasma_ctx* ctx, double* d_out);
  * E(t - dt/2) halves of E^2 and S_L, unitarity) and parks two plaquette projections in the
  * work buffer; after the step a second pass adds the E(t + dt/2) halves, E(t + dt/2) being
  * the step's own (for FP32 storage its FP32 update).  For FP64 with nt a multiple of 64 the
- * step kernel itself adds the energy slots after a Gauss-residual pass.  The non-finite
+ * step kernel itself adds the energy slots after a Gauss-residual pass.  An event of a batch
+ * has no room for the parked projections and runs glasma_observe, then the step.  The non-finite
  * slot counts detections (a site may count twice).  For the semi-implicit scheme the
  * observables pass runs between the last step's converged solve and its commit (one solve,
  * not two).  Asynchronous for the leapfrog; errors as glasma_step. */

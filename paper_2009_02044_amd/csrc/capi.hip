@@ -35,6 +35,7 @@ struct glasma_ctx {
   int adj_off0;
   const void* adj_work;
   int device;         // HIP device current when the context was created
+  bool obs_park = true;  // the work buffer holds the observing step's parked projections
   std::string err;
 };
 
@@ -139,6 +140,9 @@ static size_t work_bytes(const glasma_params* p) {
   if (p->scheme == 1) return semi_region(p).end;
   return general_bytes(p) + align256(obs_split_scratch_elems(geom_of(p), p->nc * p->nc - 1) * elem(p));
 }
+// The work region of an event of a batch: without the parked projections (the batch steps its
+// events itself; an event's own observing step takes the standalone pass instead).
+static size_t event_work_bytes(const glasma_params* p) { return general_bytes(p); }
 
 template <class F> static int dispatch(glasma_ctx* c, F&& f) {
   if (c->p.nc == 2 && c->p.fp == 64) return f.template operator()<Su2<double>, double>();
@@ -464,6 +468,7 @@ static int semi_observe_solved(glasma_ctx* c, const StepConst& sc, double* d_obs
 }
 
 static int advance(glasma_ctx* c, int32_t n);
+static int observe_leapfrog(glasma_ctx* c, const StepConst& sc, double* partial, double* d_out);
 
 int glasma_step(glasma_ctx* c, int32_t n) {
   if (!c) return fail(nullptr, GLASMA_E_ARG, "NULL context");
@@ -496,6 +501,16 @@ static int one_step(glasma_ctx* c, double* d_obs) {
     if (rc) return rc;
     if (d_obs && (rc = semi_observe_solved(c, sc, d_obs))) return rc;
     if ((rc = semi_commit(c, sc, links))) return rc;
+  } else if (d_obs && !(GL_OBS_FUSED64 && c->p.fp == 64 && fused_observe_geometry(c->g)) && !c->obs_park) {
+    // no room for the parked projections (an event of a batch): the standalone pass, then the step
+    int rc = observe_leapfrog(c, sc, (double*)c->b.work, d_obs);
+    if (rc) return rc;
+    dispatch(c, [&]<typename G, typename T>() -> int {
+      launch_leapfrog<G, T>(cur_U<T>(c), next_U<T>(c), (T*)c->b.E, (T*)c->b.rhoA, (T*)c->b.rhoB, c->g, sc,
+                            ru, c->stream);
+      return 0;
+    });
+    ru_done = ru;
   } else if (d_obs && !(GL_OBS_FUSED64 && c->p.fp == 64 && fused_observe_geometry(c->g))) {
     double* partial = (double*)c->b.work;
     dispatch(c, [&]<typename G, typename T>() -> int {
@@ -839,6 +854,7 @@ static int batch_sizes(const glasma_params* common, int32_t n, const int32_t* nz
     size_t b[6];
     int rc = glasma_layout(&q, b);
     if (rc) return rc;
+    b[5] = event_work_bytes(&q);
     L->ev.push_back(off);
     for (int k = 0; k < 6; ++k) off += align256(b[k]);
     items64 += (uint64_t)(geom_of(&q).V + 63) / 64;
@@ -888,6 +904,7 @@ int glasma_batch_create(const glasma_params* common, int32_t n_events, const int
     glasma_params q = event_params(common, nz[e], nt[e]);
     size_t sz[6];
     glasma_layout(&q, sz);
+    sz[5] = event_work_bytes(&q);
     char* base = b->pool + offs[e];
     glasma_buffers bf;
     void** slots[6] = {&bf.U, &bf.U_alt, &bf.E, &bf.rhoA, &bf.rhoB, &bf.work};
@@ -900,6 +917,7 @@ int glasma_batch_create(const glasma_params* common, int32_t n_events, const int
       delete b;
       return rc;
     }
+    c->obs_park = false;
     b->ev.push_back(c);
   }
   b->d_ev = (EventDesc*)(b->pool + toff);

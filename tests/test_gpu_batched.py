@@ -171,3 +171,37 @@ def test_batch_event_average_on_the_device():
     from paper_2009_02044_amd import GlasmaError
     with pytest.raises(GlasmaError):
         b.observe(17)       # more bins than the smallest N_z
+
+
+@pytest.mark.parametrize("fp", [32, 64])
+def test_event_step_observe_without_parked_projections(fp):
+    """An event of a batch has no room in its work region for the projections the observing
+    step parks: its glasma_step_observe takes the standalone observables pass, then the plain
+    step.  Against glasma_step, glasma_observe, glasma_step on a second, identical batch: the
+    same observables and final state, bitwise (the same kernels in the same order)."""
+    pkg = lattice_or_skip()
+    import torch
+    say(f"case: batch event step_observe fp{fp}")
+    evs = _events(3)
+    shapes = [(w.nz, w.nt) for w, _ in evs]
+    ba = pkg.Batch(3, shapes, fp=fp, reunit_every=8 if fp == 32 else 0)
+    bb = pkg.Batch(3, shapes, fp=fp, reunit_every=8 if fp == 32 else 0)
+    for b in (ba, bb):
+        for (w, rho), lat in zip(evs, b.events):
+            _init(lat, w, rho)
+    for e in (0, 4):   # nt = 4 and nt = 48
+        nz = shapes[e][0]
+        a, b = ba.events[e], bb.events[e]
+        oa, ob = a.obs_buffer(), b.obs_buffer()
+        a.step_observe(3, oa)
+        b.step(2)
+        b.observe(ob)
+        b.step(1)
+        ba.stream.synchronize()
+        bb.stream.synchronize()
+        torch.cuda.synchronize()
+        assert torch.equal(oa, ob), e
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("U", "E", "rhoA", "rhoB"):
+            assert np.array_equal(sa[k], sb[k]), (e, k)
+        assert pkg.Lattice.unpack_obs(oa, nz)["nonfinite"] == 0
