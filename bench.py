@@ -523,6 +523,9 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the FP32-vs-FP64 comparison on the 2048 x 192 x 192 lattice (minutes)")
     ap.add_argument("--precision-steps", type=int, default=2048)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the bounded FP32-vs-FP64 run of the 2048 x 192 x 192 precision workload "
+                         "(256 steps; --precision-study runs the full length)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -633,9 +636,21 @@ def main():
                       file=sys.stderr, flush=True)
     if args.rhic_profile > 0:
         detail["rhic200_rapidity_profile"] = run_rhic_profile(args.rhic_profile)
-    if args.precision_study:
+    if args.precision_study or not args.no_precision:
         wp = synth.PRECISION_SU3
-        detail["precision_fp32_vs_fp64"] = run_precision(wp, args.precision_steps)
+        full = args.precision_study
+        rp = run_precision(wp, args.precision_steps if full else 256, every=256 if full else 128)
+        detail["precision_fp32_vs_fp64"] = rp
+        keys = ("eps_slices_max_rel", "eps_total_rel", "pL_slices_max_rel", "pL_total_rel", "pT_slices_max_rel",
+                "pT_total_rel", "gauss_rel_fp32")
+        forms["precision_fp32_vs_fp64"] = {
+            "workload": wp.name, "lattice": rp["lattice"], "reunit_every": rp["reunit_every"],
+            "fp32_wall_s": round(rp["fp32_wall_s"], 2), "fp64_wall_s": round(rp["fp64_wall_s"], 2),
+            "rows": [{"step": r["step"], **{k: float(f"{r[k]:.3g}") for k in keys}} for r in rp["rows"]]}
+        last = rp["rows"][-1]
+        print(f"[bench] precision form {wp.name}, step {last['step']}: eps / p_L / p_T slices within "
+              f"{last['eps_slices_max_rel']:.2e} / {last['pL_slices_max_rel']:.2e} / {last['pT_slices_max_rel']:.2e} "
+              f"of FP64 (FP32 {rp['fp32_wall_s']:.1f} s, FP64 {rp['fp64_wall_s']:.1f} s)", file=sys.stderr, flush=True)
     bpsu = algorithmic_bytes_per_site_update(3, 64, w.dt / w.a_L)
     launch_bytes = bpsu * w.sites
     achieved = launch_bytes / (r64["kernel_ms"] * 1e-3) / 1e9
