@@ -329,7 +329,7 @@ int glasma_slab_energy(glasma_ctx* ctx, int32_t z0, int32_t z1, double* L);
 /* ---- Batched form ---------------------------------------------------------
  * Many independent events (one MV collision each) of different lattice sizes share
  * one pool of device memory and advance together: one launch per step covers every
- * event (workgroups loop over (event, block of sites) items), and glasma_batch_run
+ * event ((event, block of sites) work items), and glasma_batch_run
  * replays a captured HIP graph of `graph_chunk` steps.  The leapfrog scheme only;
  * reunitarisation (reunit_every) is fused into the step.  Each event is a regular
  * context (glasma_batch_event) for initial conditions, observables and state I/O,

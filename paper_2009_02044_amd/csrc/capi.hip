@@ -788,7 +788,7 @@ int glasma_host_group_op(int32_t nc, int32_t fp, int32_t op, int64_t n, const do
 
 // ============================================================================
 // Batched form: many events of different lattice sizes advanced together by one
-// launch per step (workgroups loop over (event, block) work items), replayed from a
+// launch per step over (event, block of sites) work items, replayed from a
 // captured HIP graph.  Each event is a full context over its own slice of the pool.
 // ============================================================================
 struct glasma_batch {

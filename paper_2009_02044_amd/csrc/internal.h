@@ -11,7 +11,7 @@ template <typename G, typename T>
 void launch_leapfrog(const T* U, T* Unew, T* E, T* rhoA, T* rhoB, const Geom& g, const StepConst& c,
                      bool reunit, hipStream_t st);
 
-// Batched form (step.hip): one descriptor per event, workgroups loop over work items.
+// Batched form (step.hip): one descriptor per event, work items of blockDim.x sites.
 // Buffers are byte offsets into the batch's pool, whose base is a kernel argument (so
 // the compiler knows every access is to device memory).
 struct EventDesc {

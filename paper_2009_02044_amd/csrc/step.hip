@@ -272,8 +272,8 @@ template void launch_leapfrog_observe<Su2<double>, double>(const double*, double
 
 // ---- batched form: many events of different sizes in one launch --------------
 
-// Work item = `bs` consecutive sites of one event; workgroups loop over the items
-// (persistent when the grid is smaller than the item count).  The step number comes
+// Work item = `bs` consecutive sites of one event: one work-group per item, or persistent
+// work-groups that loop over the items.  The step number comes
 // from device memory so that a captured graph of several steps replays correctly:
 // parity of the link buffers, hop flag and charge offsets all follow from it.
 GL_HD int64_t hop_count_dev(int64_t s, int64_t p, int64_t q) { return ((2 * s + 1) * p + q) / (2 * q); }
