@@ -60,10 +60,15 @@ def algorithmic_bytes_per_site_update(nc, fp, dt_over_aL):
 
 
 def kernel_source_hash():
+    """sha256 (16 hex digits) of the step kernel's sources without their // comments and blank
+    lines: a change of code, not of commentary, makes the committed counters stale."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2009_02044_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2009_02044_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
