@@ -299,10 +299,13 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_observe(const T* __restrict__ U, 
   block_reduce_write<OBS_BS>(acc, Q_ALL, partial + ((int64_t)z * nbx + blockIdx.x) * NQ);
 }
 
-// Gauss residual, |rho| and the non-finite count over the step kernel's work-groups (column
-// map), for the observing step: it runs before that step, which then adds the energy
-// slots to the same partial sums.  G(x) = sum_i [E_i(x) - U_i^dag(x-i) E_i(x-i) U_i(x-i)]/a_i
-// - rho(x) at (U(t), E(t - dt/2), rho(t - dt/2)).  Partial slot of block b: z nbx + its slot.
+// Gauss residual, |rho|, link unitarity and the non-finite count over the step kernel's
+// work-groups (column map), for the observing step: it runs before that step, which then
+// adds the energy slots to the same partial sums.  G(x) = sum_i [E_i(x) - U_i^dag(x-i)
+// E_i(x-i) U_i(x-i)]/a_i - rho(x) at (U(t), E(t - dt/2), rho(t - dt/2)).  Every link U_i(y)
+// is read here exactly once, as U_i(x - i) of x = y + i, so the unitarity maximum over these
+// reads is the maximum over all links (kept out of the step kernel, whose registers are at
+// their limit).  Partial slot of block b: z nbx + its slot.
 template <typename G, typename T>
 __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, const T* __restrict__ E,
                                                    const T* __restrict__ rhoA, const T* __restrict__ rhoB,
@@ -318,6 +321,7 @@ __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, cons
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  bool bad = false;
   if (has) {
     A G_, r, rb;
     load_alg(r, rhoA, 0, site_index(g, x.x, x.y, slotA(x.z, c.offA, g.nz)), Vp);
@@ -329,6 +333,9 @@ __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, cons
       const uint32_t sm = idx(g, shifted(g, x, i, -1));
       L Um;
       load_link(Um, U, i, sm, Vp);
+      const double uv = G::unit_violation(Um);
+      acc[Q_UNIT] = fmax(acc[Q_UNIT], uv);
+      bad |= !isfinite(uv);
       A eh, em;
       load_alg(eh, E, i, s, Vp);
       load_alg(em, E, i, sm, Vp);
@@ -340,13 +347,13 @@ __global__ void __launch_bounds__(256) k_obs_gauss(const T* __restrict__ U, cons
     double gm = 0.0;
     for (int k = 0; k < NG; ++k) gm = fmax(gm, fabs(G_.c[k]));
     acc[Q_GMAX] = gm;
-    acc[Q_BAD] = isfinite(acc[Q_G2]) ? 0.0 : 1.0;
+    acc[Q_BAD] = (bad || !isfinite(acc[Q_G2])) ? 1.0 : 0.0;
   }
   int z;
   uint32_t slot;
   col_map_block(m, blockIdx.x, z, slot);
   if (z >= g.nz) return;   // idle block (uniform over the block)
-  const unsigned mask = (1u << Q_G2) | (1u << Q_RHO2) | (1u << Q_GMAX) | (1u << Q_BAD);
+  const unsigned mask = (1u << Q_G2) | (1u << Q_RHO2) | (1u << Q_GMAX) | (1u << Q_UNIT) | (1u << Q_BAD);
   block_reduce_write<256>(acc, mask, partial + ((int64_t)z * nbx + slot) * NQ);
 }
 

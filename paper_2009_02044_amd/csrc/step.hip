@@ -39,12 +39,13 @@ constexpr int LF_BS = 256;
 
 // Observables gathered by an observing step (FP64): the E and B parts of T^{mu nu} at the
 // integer time of the state the step starts from (E averaged over the two half steps,
-// B from the forward plaquettes), the worst link unitarity and a non-finite flag.  The
+// B from the forward plaquettes) and a non-finite flag (the Gauss-residual pass before the
+// step measures the link unitarity).  The
 // plaquette sums hand it each forward plaquette (plane<K>); the S_L terms are formed
 // there, with E_i(t + dt/2) computed as the link update computes it, so that no
 // projection stays live until the link update.
 template <typename G, typename T> struct ObsAcc {
-  double EL2 = 0.0, ET2 = 0.0, sl = 0.0, uv = 0.0;
+  double EL2 = 0.0, ET2 = 0.0, sl = 0.0;
   bool bad = false;
   const T* E;
   uint32_t s;
@@ -118,9 +119,6 @@ __device__ __forceinline__ void finish_link(const typename G::Link& Ui, const ty
     if (i == 2) oa->EL2 = e2; else oa->ET2 += e2;
 #pragma unroll
     for (int k = 0; k < NG; ++k) oa->bad |= !isfinite((double)e.c[k]);
-    const double uv = (double)G::unit_violation(Ui);
-    oa->bad |= !isfinite(uv);
-    oa->uv = fmax(oa->uv, uv);
   }
   L Un = G::template expi_mul<true>(e, (T)(ai * c.dt), Ui);
   if (reunit) {
@@ -214,12 +212,11 @@ __global__ void __launch_bounds__(LF_BS, OBS ? 2 : GL_LF_WAVES) k_leapfrog(const
     acc[Q_PL] = 0.5 * (oa.ET2 + BT2 - oa.EL2 - BL2);
     acc[Q_PT] = 0.5 * (oa.EL2 + BL2);
     acc[Q_SL] = oa.sl;
-    acc[Q_UNIT] = oa.uv;
     acc[Q_BAD] = (oa.bad || !isfinite(acc[Q_EPS])) ? 1.0 : 0.0;
     int zb;
     uint32_t slot;
     col_map_block(m, blockIdx.x, zb, slot);
-    const unsigned mask = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_UNIT) | (1u << Q_BAD);
+    const unsigned mask = (1u << Q_EPS) | (1u << Q_PL) | (1u << Q_PT) | (1u << Q_SL) | (1u << Q_BAD);
     block_reduce_write<LF_BS, 1u << Q_BAD>(acc, mask, partial + ((int64_t)x.z * col_map_slots_per_layer(m) + slot) * NQ);
   }
 }
