@@ -584,16 +584,15 @@ __global__ void __launch_bounds__(OBS_BS, 2) k_obs_pre(const T* __restrict__ U, 
       const uint32_t sm = idx(g, shifted(g, x, i, -1));
       L Um;
       load_link(Um, U, i, sm, Vp);
+      // every link is read here once, as U_i(x - i) of x = y + i: the unitarity maximum
+      const double uv = G::unit_violation(Um);
+      bad |= !isfinite(uv);
+      acc[Q_UNIT] = fmax(acc[Q_UNIT], uv);
       A eh, em;
       load_alg(eh, E, i, s, Vp);
       load_alg(em, E, i, sm, Vp);
       const A tt = G::transport(Um, em);
       for (int k = 0; k < NG; ++k) G_.c[k] += (eh.c[k] - tt.c[k]) / ai;
-      L Ui;
-      fetch(Ui, i, s);
-      const double uv = G::unit_violation(Ui);
-      bad |= !isfinite(uv);
-      acc[Q_UNIT] = fmax(acc[Q_UNIT], uv);
     }
     acc[Q_G2] = norm2(G_);
     acc[Q_RHO2] = norm2(r);
