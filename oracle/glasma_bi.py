@@ -12,8 +12,8 @@ longitudinal fields (g = 1, hermitian algebra elements, sum over i = x, y):
     B_z = -i ([alpha_A^x, alpha_B^y] - [alpha_A^y, alpha_B^x]),
 and the energy density eps_0 = (E_z^2 + B_z^2) / 2 = p_T, p_L = -eps_0.
 
-Lattice reading (parity of this reading unpinned against the paper, which gives the
-continuum formula only): alpha^i_N lives on the transverse link (x, x + i) of the
+Lattice reading (the paper gives the continuum formula only; the reading is pinned against
+it by its convergence, below): alpha^i_N lives on the transverse link (x, x + i) of the
 lattice, alpha^i_N = P(V_N(x) V_N^dag(x + i)) / a_T with P the hermitian traceless part
 of (W - W^dag)/(2i) (the nucleus' own transverse link U_i^N = exp(i a_T alpha^i_N) to
 first order); E_z is taken at the site, averaging each commutator over the two links
@@ -24,8 +24,11 @@ V_N = exp(-i phi_N) for one sheet, the ordered product over the sheets otherwise
 
 Pinned by tests/test_oracle_bi.py: closed forms for constant SU(2) fields (E_z and B_z
 from a single commutator of generators), zero for commuting fields, invariance under
-global colour rotations, E_z odd and B_z even under A <-> B, and the weak-field limit of
-alpha against the lattice derivative of phi.
+global colour rotations, E_z odd and B_z even under A <-> B, the weak-field limit of
+alpha against the lattice derivative of phi, and convergence to the continuum formula:
+for smooth, strongly non-abelian Wilson lines on a periodic square, E_z at the sites and
+B_z at the plaquette centres approach the continuum commutators of alpha^i = -i V d_i V^dag
+at second order in the spacing.
 """
 import numpy as np
 

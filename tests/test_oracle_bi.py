@@ -67,3 +67,57 @@ def test_alpha_is_the_lattice_gradient_in_the_weak_field_limit():
         gx = eps * (np.roll(phi, -1, axis=1) - phi) / a_T
         gy = eps * (np.roll(phi, -1, axis=0) - phi) / a_T
         assert np.abs(ax - gx).max() < 10 * eps ** 2 and np.abs(ay - gy).max() < 10 * eps ** 2
+
+
+def _smooth_phi(nc, seed, X, Y, L):
+    """A smooth periodic algebra field phi(x, y) = sum_m c_m^a t^a cos(2 pi (k_m . x) / L + d_m)
+    with O(1) components along non-commuting generators."""
+    rng = np.random.default_rng(seed)
+    ng = nc * nc - 1
+    out = np.zeros(X.shape + (ng,))
+    for (kx, ky) in ((1, 0), (0, 1), (1, 1), (2, -1)):
+        c = rng.normal(0.0, 0.6, ng)
+        d = rng.uniform(0, 2 * np.pi)
+        out += np.cos(2 * np.pi * (kx * X + ky * Y) / L + d)[..., None] * c
+    return su.from_components(out, nc)
+
+
+def _continuum_fields(nc, seeds, X, Y, L, h=1e-5):
+    """The paper's continuum tau = 0+ fields at points (X, Y) for V_N = exp(-i phi_N):
+    alpha^i = -i V d_i V^dag (pure gauge), E_z = -i sum_i [alpha_A^i, alpha_B^i],
+    B_z = -i ([alpha_A^x, alpha_B^y] - [alpha_A^y, alpha_B^x]); d_i by central differences."""
+    al = []
+    for sd in seeds:
+        V = su.expi(-_smooth_phi(nc, sd, X, Y, L))
+        dx = (su.expi(_smooth_phi(nc, sd, X + h, Y, L)) - su.expi(_smooth_phi(nc, sd, X - h, Y, L))) / (2 * h)
+        dy = (su.expi(_smooth_phi(nc, sd, X, Y + h, L)) - su.expi(_smooth_phi(nc, sd, X, Y - h, L))) / (2 * h)
+        al.append((-1j * V @ dx, -1j * V @ dy))
+    (axA, ayA), (axB, ayB) = al
+    Ez = bi._com(axA, axB) + bi._com(ayA, ayB)
+    Bz = bi._com(axA, ayB) - bi._com(ayA, axB)
+    return Ez, Bz
+
+
+@pytest.mark.parametrize("nc", [2, 3])
+def test_lattice_fields_converge_to_the_continuum_formula(nc):
+    """The lattice reading of the tau = 0+ fields (alpha on the transverse links, E_z at the
+    sites, B_z at the plaquette centres) against the paper's continuum formula (Sec. 2, eqs.
+    glasma_ic1/2) for smooth, strongly non-abelian Wilson lines on a periodic square of side L:
+    the error falls by ~4 per halving of the spacing (second order)."""
+    L = 12.0
+    errs = []
+    for n in (32, 64, 128):
+        a = L / n
+        j = np.arange(n) * a
+        X, Y = np.meshgrid(j, j)                      # [y, x]
+        alA = bi.transverse_alpha(su.expi(-_smooth_phi(nc, 1, X, Y, L)), a)
+        alB = bi.transverse_alpha(su.expi(-_smooth_phi(nc, 2, X, Y, L)), a)
+        Ez, Bz = bi.bi_fields(alA, alB)
+        Ez_c, _ = _continuum_fields(nc, (1, 2), X, Y, L)
+        _, Bz_c = _continuum_fields(nc, (1, 2), X + a / 2, Y + a / 2, L)
+        assert np.abs(Ez_c).max() > 0.1 and np.abs(Bz_c).max() > 0.1     # genuinely non-abelian
+        errs.append((np.abs(Ez - Ez_c).max() / np.abs(Ez_c).max(), np.abs(Bz - Bz_c).max() / np.abs(Bz_c).max()))
+    for q in (0, 1):
+        r1, r2 = errs[0][q] / errs[1][q], errs[1][q] / errs[2][q]
+        assert 3.5 < r1 < 4.5 and 3.7 < r2 < 4.3, (q, errs)
+    assert errs[2][0] < 1e-2 and errs[2][1] < 1e-2, errs
