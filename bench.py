@@ -521,7 +521,7 @@ def main():
     ap.add_argument("--no-rest-frame", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
     ap.add_argument("--no-bi-limit", action="store_true")
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default=os.path.join("results", "bench_detail.json"),
                     help="file for the full results (per-layer arrays, tables); the printed line holds scalars")
     ap.add_argument("--rhic-profile", type=int, default=0,
                     help="also run the RHIC 200 GeV rapidity-profile study with this many events per m")
